@@ -1,0 +1,316 @@
+"""Oracle pins: check-node rules, decoders, exact marginals and ML bounds.
+
+  * CN rules against brute force over the configurations of one check
+    (min-sum output = min-marginal difference; BP output = log-ratio of the
+    parity-constrained probability sums), and against the closed transfer
+    functions of eq. (transfer_all).
+  * Decoders on tree-shaped Tanner graphs against exact marginals (BP) and
+    exact min-marginals (MS), by enumeration.
+  * Brute-force maximum-likelihood decoding of 14-qubit GB codes: every
+    decoder's exact FER is at least the ML FER; the Monte Carlo FER of the
+    oracle's sampler + decoder lies in the Wilson interval of the exact FER.
+  * Special cases and invariants: SMS(1) = MS, SAGMS(a, a, 1) = SMS(a),
+    zero syndrome, converged => H e_hat = s, round-1 closed form.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import analysis, channel, codes, decoders, judge, stats
+from oracle.decoders import DecoderParams, TannerGraph
+
+
+# ---------------------------------------------------------------- CN rules
+def _configs(d, parity):
+    return [c for c in itertools.product((0, 1), repeat=d) if sum(c) % 2 == parity]
+
+
+def brute_cn_minsum(llrs, s):
+    """Min-sum CN message to one edge: min cost with x_j = 1 minus x_j = 0."""
+    def best(par):
+        return min(sum(x * l for x, l in zip(c, llrs)) for c in _configs(len(llrs), par))
+    # x_j = 0 needs the others' parity = s, x_j = 1 needs s xor 1
+    return best(s ^ 1) - best(s)
+
+
+def brute_cn_bp(llrs, s):
+    p1 = [1.0 / (1.0 + math.exp(l)) for l in llrs]     # P(x = 1) from the LLR
+
+    def mass(par):
+        return sum(math.prod(p if x else 1 - p for x, p in zip(c, p1)) for c in _configs(len(llrs), par))
+    return math.log(mass(s) / mass(s ^ 1))
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_cn_minsum_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    d = int(rng.integers(2, 9))
+    v = rng.normal(0, 3, size=d)
+    if seed % 3 == 0:                       # exact ties and zeros
+        v[: d // 2] = np.round(v[: d // 2])
+        v[0] = 0.0
+        v[-1] = -abs(v[1])
+    s = int(rng.integers(0, 2))
+    out = decoders.cn_minsum(v[None, None, :], np.array([[s]]), np.ones((1, 1)))[0, 0]
+    for j in range(d):
+        ref = brute_cn_minsum([v[k] for k in range(d) if k != j], s)
+        if ref == 0.0:
+            assert out[j] == 0.0
+        else:
+            assert out[j] == pytest.approx(ref, abs=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_cn_bp_brute_force(seed):
+    rng = np.random.default_rng(100 + seed)
+    d = int(rng.integers(2, 8))
+    v = rng.normal(0, 2.5, size=d)
+    s = int(rng.integers(0, 2))
+    out = decoders.cn_bp(v[None, None, :], np.array([[s]]))[0, 0]
+    for j in range(d):
+        ref = brute_cn_bp([v[k] for k in range(d) if k != j], s)
+        assert out[j] == pytest.approx(ref, rel=1e-9, abs=1e-12)
+
+
+@pytest.mark.parametrize("dc", [2, 4, 10, 16])
+@pytest.mark.parametrize("kappa", [0.3, 1.0, 3.37, 8.0])
+def test_cn_transfer_functions(dc, kappa):
+    # eq. (transfer_all): every other input equal to kappa (UMA)
+    v = np.full((1, 1, dc), kappa)
+    s0 = np.zeros((1, 1), dtype=np.uint8)
+    assert decoders.cn_minsum(v, s0, np.ones((1, 1)))[0, 0, 0] == kappa
+    assert decoders.cn_minsum(v, s0, np.full((1, 1), 0.75))[0, 0, 0] == pytest.approx(0.75 * kappa)
+    bp = decoders.cn_bp(v, s0)[0, 0, 0]
+    assert bp == pytest.approx(analysis.t_bp(kappa, dc), rel=1e-9)
+    assert bp <= kappa                       # T_BP4 <= kappa (Section II)
+    # syndrome bit flips the sign
+    assert decoders.cn_minsum(v, np.ones((1, 1), dtype=np.uint8), np.ones((1, 1)))[0, 0, 0] == -kappa
+
+
+def test_bp_output_cap():
+    v = np.full((1, 1, 4), 60.0)
+    out = decoders.cn_bp(v, np.zeros((1, 1), dtype=np.uint8))[0, 0, 0]
+    assert np.isfinite(out) and out == pytest.approx(2 * math.atanh(1 - 2.0 ** -40), rel=1e-6)
+
+
+# ------------------------------------------------------- tree-shaped graphs
+def random_tree_graph(rng, checks):
+    """Tanner graph with no cycles: each new check meets one old variable."""
+    rows, nvar = [], 0
+    first = int(rng.integers(2, 4))
+    rows.append(list(range(first)))
+    nvar = first
+    for _ in range(checks - 1):
+        anchor = int(rng.integers(0, nvar))
+        new = int(rng.integers(1, 3))
+        rows.append([anchor] + list(range(nvar, nvar + new)))
+        nvar += new
+    h = np.zeros((checks, nvar), dtype=np.uint8)
+    for i, r in enumerate(rows):
+        h[i, r] = 1
+    return h
+
+
+def exact_marginals(h, s, llr):
+    m, n = h.shape
+    lp = np.full(n, -np.inf)
+    lq = np.full(n, -np.inf)
+    best1 = np.full(n, np.inf)
+    best0 = np.full(n, np.inf)
+    for e in itertools.product((0, 1), repeat=n):
+        e = np.array(e)
+        if (((h.astype(int) @ e) & 1) != s).any():
+            continue
+        logp = sum(-math.log1p(math.exp(l)) if x else -math.log1p(math.exp(-l)) for x, l in zip(e, llr))
+        cost = float((e * llr).sum())
+        for j in range(n):
+            if e[j]:
+                lq[j] = np.logaddexp(lq[j], logp)
+                best1[j] = min(best1[j], cost)
+            else:
+                lp[j] = np.logaddexp(lp[j], logp)
+                best0[j] = min(best0[j], cost)
+    return lp - lq, best1 - best0
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tree_bp_exact_and_ms_min_marginals(seed):
+    rng = np.random.default_rng(seed)
+    h = random_tree_graph(rng, int(rng.integers(3, 6)))
+    m, n = h.shape
+    assert n <= 16
+    e = rng.integers(0, 2, size=n)
+    s = ((h.astype(int) @ e) & 1).astype(np.uint8)
+    llr = rng.uniform(0.3, 2.5, size=n) * rng.choice([1, 1, 1, -1], size=n)
+    lbp, lms = exact_marginals(h, s, llr)
+    g = TannerGraph(h)
+    rounds = 2 * m + 2                      # beyond the tree's diameter
+    rb = decoders.decode(g, s[None], llr, DecoderParams(kind="bp", lmax=rounds), early_exit=False)
+    assert np.allclose(rb.posterior[0], lbp, rtol=1e-9, atol=1e-9)
+    rm = decoders.decode(g, s[None], llr, DecoderParams(kind="ms", lmax=rounds), early_exit=False)
+    assert np.allclose(rm.posterior[0], lms, rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------- 14-qubit ML pins
+def exact_fers(code, p, params_list):
+    hx, hz = codes.gb_matrices(**code)
+    n = hz.shape[1]
+    lz = codes.logical_basis(hz, hx)
+    q = 2 * p / 3
+    errs = np.array(list(itertools.product((0, 1), repeat=n)), dtype=np.uint8)
+    w = errs.sum(axis=1)
+    prob = q ** w * (1 - q) ** (n - w)
+    synd = channel.syndrome(hz, errs)
+    skey = channel.pack(synd)[:, 0]
+    cls = channel.pack(((errs.astype(int) @ lz.T.astype(int)) & 1).astype(np.uint8))[:, 0]
+    # maximum likelihood: most probable logical class per syndrome
+    table = {}
+    for sk, c, pr in zip(skey, cls, prob):
+        table.setdefault(int(sk), {}).setdefault(int(c), 0.0)
+        table[int(sk)][int(c)] += pr
+    fer_ml = 1.0 - sum(max(d.values()) for d in table.values())
+    # deterministic decoders: decode every distinct syndrome once
+    uniq, inv = np.unique(skey, return_inverse=True)
+    s_uniq = channel.unpack(uniq[:, None], hz.shape[0])
+    g = TannerGraph(hz)
+    llr = np.full(n, channel.prior_llr(p))
+    out = []
+    for prm in params_list:
+        r = decoders.decode(g, s_uniq, llr, prm)
+        fail = judge.judge_logical(lz, errs, r.ehat[inv], r.converged[inv])
+        out.append(float((prob * fail).sum()))
+    return fer_ml, out, table, lz, hz
+
+
+@pytest.mark.parametrize("code", [dict(l=7, a=(0, 1), b=(0, 2)), dict(l=7, a=(0, 1, 3), b=(0, 2, 6))])
+def test_ml_lower_bounds_every_decoder(code):
+    p = 0.08
+    prms = [DecoderParams(kind="ms", lmax=30), DecoderParams(kind="sms", alpha=0.75, lmax=30),
+            DecoderParams(kind="sagms", lmax=30), DecoderParams(kind="bp", lmax=30)]
+    fer_ml, fers, *_ = exact_fers(code, p, prms)
+    assert 0.0 < fer_ml < 0.5
+    for f in fers:
+        assert f >= fer_ml - 1e-12
+
+
+def test_ml_corrects_weight_one_on_distance_three_code():
+    code = dict(l=7, a=(0, 1), b=(0, 2))
+    _, _, table, lz, hz = exact_fers(code, 0.05, [])
+    n = hz.shape[1]
+    for j in range(n):
+        e = np.zeros((1, n), dtype=np.uint8)
+        e[0, j] = 1
+        sk = int(channel.pack(channel.syndrome(hz, e))[0, 0])
+        c = int(channel.pack(((e.astype(int) @ lz.T.astype(int)) & 1).astype(np.uint8))[0, 0])
+        best = max(table[sk].items(), key=lambda kv: kv[1])[0]
+        assert best == c
+
+
+def test_monte_carlo_fer_inside_wilson_of_exact():
+    code = dict(l=7, a=(0, 1), b=(0, 2))
+    p = 0.1
+    prm = DecoderParams(kind="sagms", lmax=30)
+    _, (fer_exact,), _, lz, hz = exact_fers(code, p, [prm])
+    f = 20000
+    ex, _ = channel.sample_paulis(11, 0, 0, f, hz.shape[1], p)
+    r = decoders.decode(TannerGraph(hz), channel.syndrome(hz, ex), np.full(14, channel.prior_llr(p)), prm)
+    fails = int(judge.judge_logical(lz, ex, r.ehat, r.converged).sum())
+    lo, hi = stats.wilson(fails, f, z=4.0)
+    assert lo <= fer_exact <= hi
+
+
+# ------------------------------------------------ invariants, special cases
+@pytest.fixture(scope="module")
+def g63_batch():
+    hx, hz = codes.gb_matrices(**codes.G63)
+    p = 0.06
+    ex, _ = channel.sample_paulis(1, 5, 0, 600, 126, p)
+    s = channel.syndrome(hz, ex)
+    return TannerGraph(hz), hz, s, np.full(126, channel.prior_llr(p))
+
+
+@pytest.mark.parametrize("arith", ["fp64", "fp32"])
+def test_sms_one_is_ms_and_sagms_constant_is_sms(g63_batch, arith):
+    g, hz, s, llr = g63_batch
+    a = decoders.decode(g, s, llr, DecoderParams(kind="ms", lmax=40), arith)
+    b = decoders.decode(g, s, llr, DecoderParams(kind="sms", alpha=1.0, lmax=40), arith)
+    assert (a.ehat == b.ehat).all() and (a.iters == b.iters).all() and (a.posterior == b.posterior).all()
+    c = decoders.decode(g, s, llr, DecoderParams(kind="sms", alpha=0.625, lmax=40), arith)
+    d = decoders.decode(g, s, llr, DecoderParams(kind="sagms", alpha_min=0.625, alpha_max=0.625,
+                                                 eta=1.0, lmax=40), arith)
+    assert (c.ehat == d.ehat).all() and (c.iters == d.iters).all() and (c.posterior == d.posterior).all()
+
+
+@pytest.mark.parametrize("kind", ["ms", "sms", "sagms", "bp"])
+@pytest.mark.parametrize("arith", ["fp64", "fp32"])
+def test_frame_invariants(g63_batch, kind, arith):
+    g, hz, s, llr = g63_batch
+    s = s.copy()
+    s[:5] = 0                                   # zero syndromes
+    prm = DecoderParams(kind=kind, lmax=25)
+    r = decoders.decode(g, s, llr, prm, arith)
+    assert (r.iters[:5] == 0).all() and not r.ehat[:5].any() and r.converged[:5].all()
+    resid = s ^ channel.syndrome(hz, r.ehat)
+    assert not resid[r.converged].any()         # converged => H e_hat = s
+    assert (r.iters[~r.converged] == prm.lmax).all()
+    assert ((r.iters >= 1) | ~s.any(axis=1)).all()
+
+
+def test_round_one_closed_form(g63_batch):
+    # After one round from v2c = L0 (uniform), every CN output is
+    # (-1)^{s_i} * prod sgn(L0) * alpha_i * L0 = (-1)^{s_i} alpha_i L0.
+    g, hz, s, llr = g63_batch
+    prm = DecoderParams(kind="sagms", lmax=1)
+    r = decoders.decode(g, s[:20], llr, prm, trace=True, early_exit=False)
+    rd = r.trace[0]
+    w = s[:20].sum(axis=1)
+    gfac = 0.50 - 0.20 * w / 63
+    for f in range(20):
+        for e in range(g.E):
+            i = g.e_check[e]
+            a = gfac[f] * (1.10 if s[f, i] else 1.0)
+            expect = (-1.0 if s[f, i] else 1.0) * a * llr[0]
+            assert rd["c2v"][f, e] == pytest.approx(expect, rel=1e-15)
+
+
+def test_gain_never_exceeds_one():
+    prm = DecoderParams(kind="sagms", alpha_min=0.3, alpha_max=0.5, eta=2.0)
+    rng = np.random.default_rng(0)
+    sres = rng.integers(0, 2, size=(200, 63)).astype(np.uint8)
+    gains = decoders.check_gains(prm, sres, 63)
+    assert gains.max() <= 1.0 and gains.min() >= 0.3 - 1e-15
+    with pytest.raises(ValueError):
+        DecoderParams(kind="sagms", alpha_max=0.6, eta=2.0).validate()
+
+
+def test_fp32_messages_track_fp64(g63_batch):
+    """FP32 messages stay within 1e-5 relative of FP64 while trajectories agree."""
+    g, hz, s, llr = g63_batch
+    prm = DecoderParams(kind="sagms", lmax=12)
+    a = decoders.decode(g, s[:200], llr, prm, "fp64", early_exit=False, trace=True)
+    b = decoders.decode(g, s[:200], llr, prm, "fp32", early_exit=False, trace=True)
+    L0 = llr[0]
+    same = np.ones(200, dtype=bool)
+    checked = 0
+    for ra, rb in zip(a.trace, b.trace):
+        same &= (ra["post"] < 0).__eq__(rb["post"] < 0).all(axis=1)
+        # compare only frames whose FP64 trajectory keeps away from sign ties
+        safe = same & (np.abs(ra["post"]).min(axis=1) > 1e-4 * L0) & (np.abs(ra["v2c"]).min(axis=1) > 1e-4 * L0)
+        if not safe.any():
+            continue
+        for key in ("c2v", "v2c", "post"):
+            x64, x32 = ra[key][safe], rb[key][safe].astype(np.float64)
+            tol = 1e-5 * np.maximum(np.abs(x64), L0)
+            assert (np.abs(x64 - x32) <= tol).all(), key
+        checked += int(safe.sum())
+    assert checked > 1000
+
+
+def test_decoder_frame_independence(g63_batch):
+    g, hz, s, llr = g63_batch
+    prm = DecoderParams(kind="sagms", lmax=30)
+    full = decoders.decode(g, s[:64], llr, prm, "fp32")
+    part = decoders.decode(g, s[20:40], llr, prm, "fp32")
+    assert (full.ehat[20:40] == part.ehat).all() and (full.iters[20:40] == part.iters).all()
