@@ -1,0 +1,166 @@
+"""Throughput benchmark of the decoding hot path on one GPU.
+
+One step = one pass of the whole path over one batch of fresh Monte Carlo
+frames: depolarizing errors + syndromes (sagms_gen_errors), SAGMS decoding
+(sagms_decode) and the logical judge (sagms_judge).  Default workload: the
+l = 63 GB code ([[126,28]], H_Z with m = 63, d_c = 10, d_v = 5, 630 edges),
+p = 0.05, 2^20 frames per step, SAGMS (alpha_min, alpha_max, eta) =
+(0.30, 0.50, 1.10), l_max = 100 with per-frame early exit, FP32 messages.
+Step s decodes frames [s * 2^20, (s + 1) * 2^20) of Philox stream 4.
+
+Prints one JSON line (see the project documentation for every field).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Peak of the bound the decoder is measured against: 32-bit VALU lane
+# operations, 256 CUs x 64 lanes x 2.4 GHz (the 157.3 TFLOP/s FP32 vector
+# figure counts an FMA as 2 flops and packed FP32 as 2 lanes).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic VALU cost of one edge-update (one c2v message produced on one
+# edge in one executed round), fixed from the paper's per-output operation
+# model restated for a wavefront implementation (see the design notes).
+OPS_PER_EDGE_UPDATE = 14
+
+
+def cpu_baseline(p, lmax, params, frames=1 << 13):
+    """The oracle (FP64, NumPy, one thread) on a bounded sample of the same
+    workload: frames 0 .. frames-1 of the same stream."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads
+    from oracle import channel, codes, decoders, judge
+    l, a, b = workloads.code("G63")
+    hx, hz = codes.gb_matrices(l, a, b)
+    tg = decoders.TannerGraph(hz)
+    lz = codes.logical_basis(hz, hx)
+    llr = np.full(2 * l, channel.prior_llr(p))
+    prm = decoders.DecoderParams(kind="sagms", lmax=lmax, **params)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        ex, _ = channel.sample_paulis(workloads.SWEEP_SEED, workloads.stream_of(p), 0, frames, 2 * l, p)
+        s = channel.syndrome(hz, ex)
+        r = decoders.decode(tg, s, llr, prm, "fp64")
+        judge.judge_logical(lz, ex, r.ehat, r.converged)
+        dt = time.perf_counter() - t0
+    return {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": "%d frames (0..%d) of the same workload, FP64 oracle: sampling + syndromes + SAGMS decode "
+                      "+ judge, %.1f s" % (frames, frames - 1, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=1 << 20)
+    ap.add_argument("--p", type=float, default=0.05)
+    ap.add_argument("--decoder", default="sagms", choices=["ms", "sms", "sagms", "bp"])
+    ap.add_argument("--alpha", type=float, default=0.75)
+    ap.add_argument("--lmax", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the decoder is data-parallel over frames and a multi-GPU run "
+              "would only split the frame range (see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2605_10433_amd as sagms
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    nf, p = args.frames, args.p
+    stream_id = workloads.stream_of(p) if p in workloads.P_GRID else 0
+    buf = sagms.frame_buffers(g, nf, device=dev)
+    llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
+    cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, **workloads.SAGMS_PARAMS)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(s, ev=None):
+        sagms.gen_errors(g, workloads.SWEEP_SEED, stream_id, s * nf, nf, p, buf["ex"], buf["ez"], buf["synd"])
+        if ev is not None:
+            ev[0].record(stream)
+        sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
+        if ev is not None:
+            ev[1].record(stream)
+        sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters)
+
+    for s in range(args.warmup):
+        step(args.steps + s)
+    torch.cuda.synchronize()
+    counters.zero_()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start.record(stream)
+    for s in range(args.steps):
+        step(s, events[s])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ms = t_start.elapsed_time(t_end)
+    dec_ms = [e0.elapsed_time(e1) for e0, e1 in events]
+    c = counters.cpu().numpy()
+    frames = nf * args.steps
+    sum_iters = int(c[1])
+    edge_updates = sum_iters * g.n_edges
+    it_last = buf["iters"].float()
+    mean_dec_ms = float(np.mean(dec_ms))
+    ops_per_launch = OPS_PER_EDGE_UPDATE * edge_updates / args.steps
+    achieved = ops_per_launch / (mean_dec_ms * 1e-3) / 1e12
+    from paper_2605_10433_amd.stats import wilson
+    fer = c[0] / frames
+    lo, hi = wilson(int(c[0]), frames)
+    out = {
+        "metric": "SAGMS frames/s",
+        "value": frames / (total_ms * 1e-3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "GB l=63 [[126,28]] (H_Z: m=63, d_c=10, d_v=5, E=630), code-capacity depolarizing "
+                               "p=%g, %d Philox frames/step, %s l_max=%d early exit, flooding, FP32 messages"
+                               % (p, nf, args.decoder.upper(), args.lmax),
+                   "code": "G63", "p": p, "frames_per_step": nf, "decoder": args.decoder, "lmax": args.lmax},
+        "edge_updates_per_s": edge_updates / (total_ms * 1e-3),
+        "decode_ms_per_step": mean_dec_ms,
+        "decode_frames_per_s": nf / (mean_dec_ms * 1e-3),
+        "mean_iters": sum_iters / frames,
+        "p99_iters_last_step": float(torch.quantile(it_last, 0.99).item()),
+        "fer": fer,
+        "fer_wilson95": [lo, hi],
+        "wall_s": wall,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "decode_kernel<10,5,1,2,false>",
+                     "ops_per_edge_update": OPS_PER_EDGE_UPDATE},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.lmax, workloads.SAGMS_PARAMS)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

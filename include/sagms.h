@@ -1,0 +1,194 @@
+/*
+ * libsagms -- batched min-sum decoding of generalized-bicycle QLDPC codes
+ * on MI355X (gfx950).  C ABI.
+ *
+ * Implements the decoding path of Cordova et al., "Syndrome Adaptive Gain
+ * Control for Min-Sum Decoding of Quantum LDPC Codes" (arXiv 2605.10433):
+ * depolarizing-noise Monte Carlo frames (Section II), their syndromes, and
+ * the MS, SMS and SAGMS decoders of Sections II-III (Algorithm 1), with the
+ * BP decoder of eq. (bp4_cn) as a comparison.  Decoding is binary: the X
+ * part of each error is decoded on the Tanner graph of one CSS check matrix
+ * (H_Z for GB codes) from its syndrome, with a per-variable prior LLR.
+ *
+ * Conventions shared by every entry point
+ *   - Status: every function returns SAGMS_OK (0) or a negative SAGMS_E*
+ *     code; sagms_last_error() then holds a message (thread-local).  No
+ *     function aborts or throws across the ABI.
+ *   - Bit vectors are packed in uint64 words: bit b of word w is index
+ *     64 w + b; unused high bits of the last word are written as zero.
+ *     A per-frame vector of nbits bits occupies words(nbits) = ceil(nbits/64)
+ *     consecutive words; frame f of a batch starts at word f * words(nbits).
+ *   - Device buffers are caller-owned device pointers (hipMalloc'd or torch
+ *     tensors) on the current HIP device; `stream` is a hipStream_t passed
+ *     as void* (NULL = the null stream).  Every device call is asynchronous
+ *     on `stream` and never synchronises.  Host pointers are named *_host.
+ *   - A graph handle is immutable after it is built and may be shared by
+ *     calls on several streams at once.  Its device tables are created on
+ *     the first device call per HIP device (one-off hipMalloc + copy).
+ */
+#ifndef SAGMS_H
+#define SAGMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SAGMS_OK 0
+#define SAGMS_EINVAL (-1)       /* bad argument (null pointer, size, range)  */
+#define SAGMS_ENOMEM (-2)       /* host or device allocation failed          */
+#define SAGMS_EUNSUPPORTED (-3) /* graph shape outside the compiled kernels   */
+#define SAGMS_EHIP (-4)         /* a HIP runtime call failed                  */
+
+/* ---- decoder selection ----------------------------------------------- */
+typedef enum {
+    SAGMS_MS = 0,    /* min-sum, eq. (ms_cn)                                */
+    SAGMS_SMS = 1,   /* min-sum scaled by a fixed alpha (Section II)        */
+    SAGMS_SAGMS = 2, /* syndrome-adaptive gain, eqs. (alphaeff), (sagms_cn) */
+    SAGMS_BP = 3     /* belief propagation, eq. (bp4_cn) (comparison)       */
+} sagms_kind;
+
+typedef enum { SAGMS_FLOODING = 0 } sagms_schedule;
+
+typedef enum {
+    SAGMS_MSG_FP32 = 0 /* FP32 messages and sums; BP evaluates its CN in FP64 */
+} sagms_msg_precision;
+
+/* Decoder configuration (Algorithm 1 inputs besides H, s and L0).
+ *   lmax       maximum number of CN/VN update rounds, >= 1
+ *   alpha      SMS scale, in (0, 1]
+ *   alpha_min, alpha_max, eta
+ *              SAGMS gain law of eq. (alphaeff): per round,
+ *              g = alpha_max - (alpha_max - alpha_min) * w / m with w the
+ *              weight of the residual syndrome and m the number of checks,
+ *              times eta at unsatisfied checks.  0 < alpha_min, alpha_max
+ *              <= 1, eta >= 1, and the stability constraint of Section III,
+ *              alpha_max * eta <= 1, is enforced (SAGMS_EINVAL otherwise).
+ * Fields not used by `kind` are ignored. */
+typedef struct {
+    int32_t kind;          /* sagms_kind          */
+    int32_t schedule;      /* sagms_schedule      */
+    int32_t lmax;
+    int32_t msg_precision; /* sagms_msg_precision */
+    double alpha;
+    double alpha_min;
+    double alpha_max;
+    double eta;
+} sagms_decoder_cfg;
+
+typedef struct sagms_graph_s* sagms_graph;
+
+typedef struct {
+    int32_t m, n;          /* checks, variables of the decoding matrix H      */
+    int32_t n_edges;       /* number of ones of H (Tanner-graph edges)        */
+    int32_t k;             /* logical dimension n - rank H - rank H_other, or
+                              -1 when no other matrix was given              */
+    int32_t dc_max, dv_max;/* largest check / variable degree                 */
+    int32_t words_n;       /* ceil(n / 64): words per error / estimate frame  */
+    int32_t words_m;       /* ceil(m / 64): words per syndrome frame          */
+} sagms_graph_info_t;
+
+/* ---- graphs (host only; no device needed) ----------------------------- */
+
+/* Tanner graph of a binary check matrix H (m x n) given in CSR form on the
+ * host: the ones of row i are col_idx[row_ptr[i] .. row_ptr[i+1]-1].
+ * Section II notation: check i has neighbours M(i), variable j has N(j).
+ * The optional other CSS matrix (m_other rows, same n) is used only by the
+ * logical judge; pass m_other = 0 and NULL pointers to omit it.
+ * Requirements: 1 <= m, 1 <= n <= 4096, column indices in [0, n), no
+ * repeated column in a row, every check degree >= 2 (SAGMS_EINVAL), and
+ * H * H_other^T = 0 over GF(2) when H_other is given (SAGMS_EINVAL).
+ * The handle is owned by the library: release it with sagms_destroy_graph. */
+int sagms_build_graph(int32_t m, int32_t n, const int32_t* row_ptr_host, const int32_t* col_idx_host,
+                      int32_t m_other, const int32_t* row_ptr_other_host,
+                      const int32_t* col_idx_other_host, sagms_graph* out);
+
+/* The GB code of circulant size l with polynomials a(x), b(x) given by their
+ * exponent lists (values in [0, l), distinct; Section II: the generalized
+ * bicycle family).  Circulant convention A[i][j] = 1 iff (j - i) mod l is an
+ * exponent of a.  Builds the decoding matrix H = H_Z = [B^T | A^T] and the
+ * other matrix H_X = [A | B], so that X errors are decoded from their H_Z
+ * syndrome.  n = 2l, m = l. */
+int sagms_build_gb(int32_t l, const int32_t* a_host, int32_t wa, const int32_t* b_host, int32_t wb,
+                   sagms_graph* out);
+
+int sagms_graph_info(sagms_graph g, sagms_graph_info_t* info);
+
+/* Copies the decoding matrix H as packed rows: row i occupies words_n words
+ * starting at rows_host + i * words_n. */
+int sagms_graph_rows(sagms_graph g, uint64_t* rows_host);
+
+/* Copies the logical basis used by the judge (k rows of words_n words): a
+ * basis of ker(H_other) modulo rowspace(H). */
+int sagms_graph_logicals(sagms_graph g, uint64_t* rows_host);
+
+int sagms_destroy_graph(sagms_graph g);
+
+/* Binary prior LLR of the X part of a depolarizing error of strength p:
+ * ln((1 - 2p/3) / (2p/3)) (the binary marginal of the prior of Section II),
+ * rounded to float.  Returns NaN for p outside (0, 0.75). */
+float sagms_prior_llr(double p);
+
+/* ---- device entry points --------------------------------------------- */
+
+/* Depolarizing errors and their syndromes (Section II, channel and syndrome).
+ * For frames frame0 .. frame0 + nframes - 1 and qubits q < n: one
+ * Philox4x32-10 block (Salmon et al., SC'11) with key (seed mod 2^32,
+ * seed >> 32) and counter (q / 4, frame mod 2^32, frame >> 32, stream_id)
+ * gives 32-bit word u = output[q mod 4]; with T_X = floor(p/3 * 2^32),
+ * T_Y = floor((2p)/3 * 2^32), T_Z = floor(p * 2^32) (IEEE double), the Pauli
+ * is X if u < T_X, Y if u < T_Y, Z if u < T_Z, else I.
+ * Outputs (device, packed): ex, ez [nframes][words_n] the X and Z parts
+ * (ez may be NULL to skip it), synd [nframes][words_m] = H e_x (mod 2).
+ * 0 <= p < 1; nframes >= 0 (0 is a no-op). */
+int sagms_gen_errors(sagms_graph g, uint64_t seed, uint32_t stream_id, uint64_t frame0, int64_t nframes,
+                     double p, uint64_t* ex, uint64_t* ez, uint64_t* synd, void* stream);
+
+/* Decode nframes syndromes (Algorithm 1, flooding schedule).
+ *   synd      device [nframes][words_m] packed syndromes s
+ *   llr0      device [n] float prior LLRs L0_j (finite; -0.0 reads as +0.0)
+ *   ehat      device [nframes][words_n] packed hard decisions e_hat
+ *   iters     device [nframes] number of CN update rounds performed:
+ *             0 if the first hard decision [L0 < 0] already satisfies s,
+ *             the round at which the residual syndrome became zero, or lmax
+ *   converged device [nframes] 1 iff s xor H e_hat = 0
+ * Each round: gains from the residual syndrome, CN update (eq. (ms_cn),
+ * scaled per eq. (alphaeff)/(sagms_cn), or eq. (bp4_cn) for BP), VN update
+ * (eq. (bp4_vn)), hard decision e_j = [posterior_j < 0], residual syndrome,
+ * exit when it is zero.  Messages are FP32; posteriors are summed in
+ * ascending check order and v2c = posterior - c2v; the BP CN runs in FP64.
+ * Per-frame results do not depend on nframes, the batch split or the
+ * stream.  nframes >= 0. */
+int sagms_decode(sagms_graph g, const uint64_t* synd, const float* llr0, const sagms_decoder_cfg* cfg,
+                 int64_t nframes, uint64_t* ehat, int32_t* iters, uint8_t* converged, void* stream);
+
+/* sagms_decode plus soft output: posterior (device, float [nframes][n],
+ * row f at posterior + f * n) receives every variable's last posterior
+ * L0_j + sum of its incoming c2v messages (the quantity whose sign is the
+ * hard decision of Algorithm 1).  Same status codes as sagms_decode. */
+int sagms_decode_soft(sagms_graph g, const uint64_t* synd, const float* llr0, const sagms_decoder_cfg* cfg,
+                      int64_t nframes, uint64_t* ehat, int32_t* iters, uint8_t* converged, float* posterior,
+                      void* stream);
+
+/* Logical-failure judge.  Frame f fails iff converged[f] == 0, or the
+ * residual r = ex xor ehat has odd overlap with some row of the logical
+ * basis (equivalently r is not in the rowspace of H_other; Section II:
+ * decoding succeeds when the residual syndrome is zero, and the residual
+ * error must be a stabilizer).  Needs a graph built with H_other.
+ *   ex, ehat  device [nframes][words_n]; converged, iters device [nframes]
+ *   fail      device [nframes] (may be NULL): 1 for a failed frame
+ *   counters  device uint64 [2], accumulated with atomics (not cleared):
+ *             counters[0] += failures, counters[1] += sum of iters */
+int sagms_judge(sagms_graph g, const uint64_t* ex, const uint64_t* ehat, const uint8_t* converged,
+                const int32_t* iters, int64_t nframes, uint8_t* fail, uint64_t* counters, void* stream);
+
+/* Message for the last non-zero status returned on this thread. */
+const char* sagms_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAGMS_H */

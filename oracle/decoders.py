@@ -9,14 +9,16 @@ syndrome with the binary prior LLR).
 
 Readings where the paper is silent or inconsistent (each listed in the
 design notes of the project):
-  * Round order.  Messages start as v2c = L0 on every edge and c2v = 0.  If
-    the syndrome is zero the frame is done after 0 rounds.  Otherwise each
-    round l = 1..lmax is: gains from the current residual syndrome, CN
-    update, VN update, posterior and hard decision, residual syndrome
-    s_res = s xor H e_hat, and exit if s_res = 0.  `iters` counts the CN
-    updates performed (l at convergence, lmax otherwise).  Algorithm 1
-    tests the residual at the top of the next round instead; the message
-    sequence is the same.
+  * Round order.  Messages start as v2c = L0 on every edge and c2v = 0, so
+    the first posterior is L0 and the first hard decision [L0 < 0] (all
+    zero for a positive prior); if its residual syndrome is zero the frame
+    is done after 0 rounds.  Otherwise each round l = 1..lmax is: gains from
+    the current residual syndrome, CN update, VN update, posterior and hard
+    decision, residual syndrome s_res = s xor H e_hat, and exit if
+    s_res = 0.  `iters` counts the CN updates performed (l at convergence,
+    lmax otherwise).  This is Algorithm 1 with its top-of-loop test also
+    applied after the lmax-th update, so that every update performed is
+    used.
   * The CN sign uses the original syndrome bit s_i (eqs. (ms_cn),
     (sagms_cn)); the residual bit s_res_i only selects the eta boost
     (eq. (alphaeff)).  |S| in the syndrome ratio is m, the number of rows
@@ -215,13 +217,15 @@ def decode(g: TannerGraph, synd, llr0, params: DecoderParams, arith: str = "fp64
     if L0.shape != (n,):
         raise ValueError("llr0 must have n entries")
 
-    ehat = np.zeros((f, n), dtype=np.uint8)
+    # round 0: posterior L0, hard decision [L0 < 0], its residual syndrome
+    e0 = (L0 < 0).astype(np.uint8)
+    ehat = np.broadcast_to(e0, (f, n)).copy()
     iters = np.zeros(f, dtype=np.int32)
     conv = np.zeros(f, dtype=bool)
     post_all = np.broadcast_to(L0, (f, n)).copy()
-    sres = synd.copy()
+    sres = synd ^ ((g.h.astype(np.int64) @ e0.astype(np.int64)) & 1).astype(np.uint8)[None, :]
     active = sres.any(axis=1) if early_exit else np.ones(f, dtype=bool)
-    conv[~synd.any(axis=1)] = True
+    conv[~sres.any(axis=1)] = True
 
     # message slots: E edges plus the padding sentinel
     v2c = np.empty((f, E + 1), dtype=dt)

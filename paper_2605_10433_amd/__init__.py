@@ -1,0 +1,244 @@
+"""Python binding of libsagms (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libsagms.so``; this module
+checks tensor shapes / dtypes / devices and passes raw device pointers and
+the current HIP stream through the C ABI declared in ``include/sagms.h``.
+PyTorch supplies device memory and streams.  Packed bit vectors (uint64
+words in the ABI) are stored in int64 tensors.
+
+Importing works without a GPU (graph construction is host code); the device
+entry points raise if no GPU is present.  If ``libsagms.so`` has not been
+built, loading raises ``ImportError`` -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsagms.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sagms.h")
+
+OK, EINVAL, ENOMEM, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
+KINDS = {"ms": 0, "sms": 1, "sagms": 2, "bp": 3}
+
+_lib = None
+
+
+class SagmsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libsagms error %d: %s" % (code, msg))
+        self.code = code
+
+
+class DecoderConfig(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("schedule", ctypes.c_int32), ("lmax", ctypes.c_int32),
+                ("msg_precision", ctypes.c_int32), ("alpha", ctypes.c_double), ("alpha_min", ctypes.c_double),
+                ("alpha_max", ctypes.c_double), ("eta", ctypes.c_double)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in
+                ("m", "n", "n_edges", "k", "dc_max", "dv_max", "words_n", "words_m")]
+
+
+def lib():
+    """The loaded libsagms (raises ImportError when it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsagms.so is not built (python -m paper_2605_10433_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                       ctypes.c_uint64, ctypes.c_double)
+        sigs = {
+            "sagms_build_graph": [i32, i32, vp, vp, i32, vp, vp, vp],
+            "sagms_build_gb": [i32, vp, i32, vp, i32, vp],
+            "sagms_graph_info": [vp, vp],
+            "sagms_graph_rows": [vp, vp],
+            "sagms_graph_logicals": [vp, vp],
+            "sagms_destroy_graph": [vp],
+            "sagms_gen_errors": [vp, u64, u32, u64, i64, dbl, vp, vp, vp, vp],
+            "sagms_decode": [vp, vp, vp, vp, i64, vp, vp, vp, vp],
+            "sagms_decode_soft": [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp],
+            "sagms_judge": [vp, vp, vp, vp, vp, i64, vp, vp, vp],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.sagms_last_error.argtypes = []
+        L.sagms_last_error.restype = ctypes.c_char_p
+        L.sagms_prior_llr.argtypes = [dbl]
+        L.sagms_prior_llr.restype = ctypes.c_float
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/sagms.h."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:int|float|const char\*)\s+(sagms_\w+)\s*\(", text, flags=re.M)))
+
+
+def _check(rc):
+    if rc != OK:
+        raise SagmsError(rc, lib().sagms_last_error().decode())
+
+
+def prior_llr(p: float) -> float:
+    return float(lib().sagms_prior_llr(float(p)))
+
+
+def decoder_config(kind="sagms", lmax=100, alpha=0.75, alpha_min=0.30, alpha_max=0.50, eta=1.10) -> DecoderConfig:
+    if kind not in KINDS:
+        raise ValueError("unknown decoder kind %r" % kind)
+    return DecoderConfig(KINDS[kind], 0, int(lmax), 0, float(alpha), float(alpha_min), float(alpha_max), float(eta))
+
+
+class Graph:
+    """An immutable Tanner graph handle owned by libsagms."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+        info = GraphInfo()
+        _check(lib().sagms_graph_info(self._h, ctypes.byref(info)))
+        for name, _ in GraphInfo._fields_:
+            setattr(self, name, int(getattr(info, name)))
+
+    @classmethod
+    def gb(cls, l, a, b):
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        b = np.ascontiguousarray(b, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().sagms_build_gb(int(l), a.ctypes.data, len(a), b.ctypes.data, len(b), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_dense(cls, h, h_other=None):
+        def csr(mat):
+            mat = np.asarray(mat, dtype=np.uint8)
+            rp = np.zeros(mat.shape[0] + 1, dtype=np.int32)
+            cols = []
+            for i, row in enumerate(mat):
+                nz = np.nonzero(row & 1)[0]
+                cols.extend(nz.tolist())
+                rp[i + 1] = len(cols)
+            return rp, np.asarray(cols, dtype=np.int32)
+        h = np.asarray(h)
+        rp, ci = csr(h)
+        hdl = ctypes.c_void_p()
+        if h_other is None:
+            _check(lib().sagms_build_graph(h.shape[0], h.shape[1], rp.ctypes.data, ci.ctypes.data, 0, None, None,
+                                           ctypes.byref(hdl)))
+        else:
+            rpo, cio = csr(h_other)
+            _check(lib().sagms_build_graph(h.shape[0], h.shape[1], rp.ctypes.data, ci.ctypes.data,
+                                           np.asarray(h_other).shape[0], rpo.ctypes.data, cio.ctypes.data,
+                                           ctypes.byref(hdl)))
+        return cls(hdl.value)
+
+    def rows(self) -> np.ndarray:
+        out = np.zeros((self.m, self.words_n), dtype=np.uint64)
+        _check(lib().sagms_graph_rows(self._h, out.ctypes.data))
+        return out
+
+    def logicals(self) -> np.ndarray:
+        out = np.zeros((max(self.k, 0), self.words_n), dtype=np.uint64)
+        _check(lib().sagms_graph_logicals(self._h, out.ctypes.data))
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().sagms_destroy_graph(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- device entry points ------------------------------------------------
+def _dev_ptr(t, dtype, shape, name):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s (got %s)" % (name, tuple(shape), tuple(t.shape)))
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def gen_errors(g: Graph, seed, stream_id, frame0, nframes, p, ex, ez, synd, stream=None):
+    import torch
+    _check(lib().sagms_gen_errors(
+        g._h, int(seed), int(stream_id), int(frame0), int(nframes), float(p),
+        _dev_ptr(ex, torch.int64, (nframes, g.words_n), "ex"),
+        _dev_ptr(ez, torch.int64, (nframes, g.words_n), "ez"),
+        _dev_ptr(synd, torch.int64, (nframes, g.words_m), "synd"), _stream(stream)))
+
+
+def decode(g: Graph, synd, llr0, cfg: DecoderConfig, ehat, iters, converged, stream=None):
+    import torch
+    nframes = synd.shape[0]
+    _check(lib().sagms_decode(
+        g._h, _dev_ptr(synd, torch.int64, (nframes, g.words_m), "synd"),
+        _dev_ptr(llr0, torch.float32, (g.n,), "llr0"), ctypes.byref(cfg), int(nframes),
+        _dev_ptr(ehat, torch.int64, (nframes, g.words_n), "ehat"),
+        _dev_ptr(iters, torch.int32, (nframes,), "iters"),
+        _dev_ptr(converged, torch.uint8, (nframes,), "converged"), _stream(stream)))
+
+
+def decode_soft(g: Graph, synd, llr0, cfg: DecoderConfig, ehat, iters, converged, posterior, stream=None):
+    import torch
+    nframes = synd.shape[0]
+    _check(lib().sagms_decode_soft(
+        g._h, _dev_ptr(synd, torch.int64, (nframes, g.words_m), "synd"),
+        _dev_ptr(llr0, torch.float32, (g.n,), "llr0"), ctypes.byref(cfg), int(nframes),
+        _dev_ptr(ehat, torch.int64, (nframes, g.words_n), "ehat"),
+        _dev_ptr(iters, torch.int32, (nframes,), "iters"),
+        _dev_ptr(converged, torch.uint8, (nframes,), "converged"),
+        _dev_ptr(posterior, torch.float32, (nframes, g.n), "posterior"), _stream(stream)))
+
+
+def judge(g: Graph, ex, ehat, converged, iters, counters, fail=None, stream=None):
+    import torch
+    nframes = ex.shape[0]
+    _check(lib().sagms_judge(
+        g._h, _dev_ptr(ex, torch.int64, (nframes, g.words_n), "ex"),
+        _dev_ptr(ehat, torch.int64, (nframes, g.words_n), "ehat"),
+        _dev_ptr(converged, torch.uint8, (nframes,), "converged"),
+        _dev_ptr(iters, torch.int32, (nframes,), "iters"), int(nframes),
+        _dev_ptr(fail, torch.uint8, (nframes,), "fail"),
+        _dev_ptr(counters, torch.int64, (2,), "counters"), _stream(stream)))
+
+
+def frame_buffers(g: Graph, nframes: int, device="cuda", with_ez=True):
+    """Device tensors for one batch: ex, ez, synd, ehat, iters, converged, fail."""
+    import torch
+    z = dict(device=device)
+    return dict(
+        ex=torch.empty((nframes, g.words_n), dtype=torch.int64, **z),
+        ez=torch.empty((nframes, g.words_n), dtype=torch.int64, **z) if with_ez else None,
+        synd=torch.empty((nframes, g.words_m), dtype=torch.int64, **z),
+        ehat=torch.empty((nframes, g.words_n), dtype=torch.int64, **z),
+        iters=torch.empty((nframes,), dtype=torch.int32, **z),
+        converged=torch.empty((nframes,), dtype=torch.uint8, **z),
+        fail=torch.empty((nframes,), dtype=torch.uint8, **z),
+    )

@@ -1,0 +1,418 @@
+// Host side of libsagms: Tanner graphs, GF(2) algebra for the logical
+// judge, per-device tables, error reporting and the graph entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace sagms {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SAGMS_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+// ---- GF(2) elimination on packed rows ----------------------------------
+static inline bool bit(const uint64_t* row, int j) { return (row[j >> 6] >> (j & 63)) & 1u; }
+
+// Reduces `rows` (nrows x wn words) in place to row-echelon form; returns the
+// rank and the pivot column of each of the first `rank` rows.
+static int gf2_echelon(std::vector<uint64_t>& rows, int nrows, int wn, int ncols, std::vector<int>* pivots) {
+    int r = 0;
+    for (int c = 0; c < ncols && r < nrows; ++c) {
+        int p = -1;
+        for (int i = r; i < nrows; ++i)
+            if (bit(&rows[(size_t)i * wn], c)) { p = i; break; }
+        if (p < 0) continue;
+        if (p != r)
+            for (int w = 0; w < wn; ++w) std::swap(rows[(size_t)p * wn + w], rows[(size_t)r * wn + w]);
+        for (int i = 0; i < nrows; ++i)
+            if (i != r && bit(&rows[(size_t)i * wn], c))
+                for (int w = 0; w < wn; ++w) rows[(size_t)i * wn + w] ^= rows[(size_t)r * wn + w];
+        if (pivots) pivots->push_back(c);
+        ++r;
+    }
+    return r;
+}
+
+int gf2_rank(std::vector<uint64_t> rows, int nrows, int wn) {
+    return gf2_echelon(rows, nrows, wn, wn * 64, nullptr);
+}
+
+// Basis of {x : A x = 0} for A given as packed rows.
+static std::vector<uint64_t> gf2_kernel(std::vector<uint64_t> a, int nrows, int wn, int ncols, int* dim) {
+    std::vector<int> piv;
+    int r = gf2_echelon(a, nrows, wn, ncols, &piv);
+    std::vector<char> is_piv(ncols, 0);
+    for (int c : piv) is_piv[c] = 1;
+    std::vector<uint64_t> out;
+    int d = 0;
+    for (int f = 0; f < ncols; ++f) {
+        if (is_piv[f]) continue;
+        std::vector<uint64_t> v(wn, 0);
+        v[f >> 6] |= 1ull << (f & 63);
+        for (int i = 0; i < r; ++i)
+            if (bit(&a[(size_t)i * wn], f)) v[piv[i] >> 6] |= 1ull << (piv[i] & 63);
+        out.insert(out.end(), v.begin(), v.end());
+        ++d;
+    }
+    *dim = d;
+    return out;
+}
+
+// ---- decode shapes and LDS layout ----------------------------------------
+static const DecodeShape kShapes[] = {
+    {4, 2, 1, 1},  {6, 3, 1, 1},  {10, 5, 1, 2}, {16, 8, 1, 2}, {10, 5, 2, 4},
+    {16, 8, 2, 4}, {6, 3, 4, 8},  {8, 4, 4, 8},  {10, 5, 8, 16},
+};
+
+bool pick_shape(int m, int n, int dc, int dv, DecodeShape* out) {
+    bool found = false;
+    int best = 0;
+    for (const DecodeShape& s : kShapes) {
+        if (s.dc < dc || s.dv < dv || 64 * s.cpl < m || 64 * s.vpl < n) continue;
+        int cost = s.cpl * s.dc * 3 + s.vpl * s.dv;  // registers held per lane, roughly
+        if (!found || cost < best) { *out = s; best = cost; found = true; }
+    }
+    return found;
+}
+
+DecodeLayout make_layout(const DecodeShape& s) {
+    DecodeLayout L;
+    L.cw = 64 * s.cpl;
+    L.zero = s.dc * L.cw;
+    L.post0 = L.zero + 1;
+    L.padpost = L.post0 + 64 * s.vpl;
+    L.gain0 = (L.padpost + 2) & ~1;  // 8-byte aligned pairs
+    L.words = L.gain0 + 2 * (L.cw + 1);
+    return L;
+}
+
+// Builds the per-lane LDS address tables for the chosen shape.
+static void build_lane_tables(Graph* g) {
+    const DecodeShape& s = g->shape;
+    const DecodeLayout& L = g->layout;
+    g->cn_addr_host.assign((size_t)s.cpl * s.dc * 64, (uint32_t)L.padpost);
+    g->vn_addr_host.assign((size_t)s.vpl * s.dv * 64, (uint32_t)L.zero);
+    // variable -> (check, position) in ascending check order
+    std::vector<std::vector<std::pair<int, int>>> adj(g->n);
+    for (int c = 0; c < g->m; ++c)
+        for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p) {
+            int j = g->cols[g->row_ptr[c] + p];
+            adj[j].push_back({c, p});
+            g->cn_addr_host[((size_t)(c / 64) * s.dc + p) * 64 + (c % 64)] = (uint32_t)(L.post0 + j);
+        }
+    for (int j = 0; j < g->n; ++j) {
+        std::sort(adj[j].begin(), adj[j].end());
+        for (size_t r = 0; r < adj[j].size(); ++r) {
+            int c = adj[j][r].first, p = adj[j][r].second;
+            g->vn_addr_host[((size_t)(j / 64) * s.dv + r) * 64 + (j % 64)] = (uint32_t)(p * L.cw + c);
+        }
+    }
+}
+
+// ---- graph construction ------------------------------------------------
+static int finish_graph(Graph* g, const std::vector<int>& row_ptr_o, const std::vector<int>& cols_o, int m_other) {
+    g->E = g->row_ptr[g->m];
+    g->wn = (g->n + 63) / 64;
+    g->wm = (g->m + 63) / 64;
+    g->rows_bits.assign((size_t)g->m * g->wn, 0);
+    std::vector<int> vdeg(g->n, 0);
+    g->dc_max = 0;
+    for (int c = 0; c < g->m; ++c) {
+        int d = g->row_ptr[c + 1] - g->row_ptr[c];
+        g->dc_max = std::max(g->dc_max, d);
+        for (int t = g->row_ptr[c]; t < g->row_ptr[c + 1]; ++t) {
+            int j = g->cols[t];
+            g->rows_bits[(size_t)c * g->wn + (j >> 6)] |= 1ull << (j & 63);
+            vdeg[j]++;
+        }
+    }
+    g->dv_max = g->n ? *std::max_element(vdeg.begin(), vdeg.end()) : 0;
+    g->have_other = m_other > 0;
+    if (g->have_other) {
+        std::vector<uint64_t> other((size_t)m_other * g->wn, 0);
+        for (int c = 0; c < m_other; ++c)
+            for (int t = row_ptr_o[c]; t < row_ptr_o[c + 1]; ++t)
+                other[(size_t)c * g->wn + (cols_o[t] >> 6)] |= 1ull << (cols_o[t] & 63);
+        // CSS condition: every row of H is orthogonal to every row of H_other
+        for (int a = 0; a < g->m; ++a)
+            for (int b = 0; b < m_other; ++b) {
+                int par = 0;
+                for (int w = 0; w < g->wn; ++w)
+                    par ^= __builtin_popcountll(g->rows_bits[(size_t)a * g->wn + w] & other[(size_t)b * g->wn + w]) & 1;
+                if (par) return fail(SAGMS_EINVAL, "row %d of H and row %d of H_other anticommute", a, b);
+            }
+        // logical basis: ker(H_other) modulo rowspace(H)
+        int kdim = 0;
+        std::vector<uint64_t> kern = gf2_kernel(other, m_other, g->wn, g->n, &kdim);
+        std::vector<uint64_t> acc = g->rows_bits;
+        int acc_rows = g->m;
+        int acc_rank = gf2_rank(acc, acc_rows, g->wn);
+        g->logicals.clear();
+        for (int t = 0; t < kdim; ++t) {
+            std::vector<uint64_t> trial = acc;
+            trial.insert(trial.end(), kern.begin() + (size_t)t * g->wn, kern.begin() + (size_t)(t + 1) * g->wn);
+            int r = gf2_rank(trial, acc_rows + 1, g->wn);
+            if (r > acc_rank) {
+                acc.swap(trial);
+                acc_rows++;
+                acc_rank = r;
+                g->logicals.insert(g->logicals.end(), kern.begin() + (size_t)t * g->wn,
+                                   kern.begin() + (size_t)(t + 1) * g->wn);
+            }
+        }
+        g->k = (int)(g->logicals.size() / g->wn);
+    }
+    g->shape_ok = pick_shape(g->m, g->n, g->dc_max, g->dv_max, &g->shape);
+    if (g->shape_ok) {
+        g->layout = make_layout(g->shape);
+        build_lane_tables(g);
+    }
+    return SAGMS_OK;
+}
+
+static int check_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, const char* name, bool need_deg2) {
+    if (!rp || !ci) return fail(SAGMS_EINVAL, "%s: null CSR pointer", name);
+    if (rp[0] != 0) return fail(SAGMS_EINVAL, "%s: row_ptr[0] must be 0", name);
+    std::vector<char> seen(n, 0);
+    for (int i = 0; i < m; ++i) {
+        if (rp[i + 1] < rp[i]) return fail(SAGMS_EINVAL, "%s: row_ptr decreases at row %d", name, i);
+        if (need_deg2 && rp[i + 1] - rp[i] < 2)
+            return fail(SAGMS_EINVAL, "%s: check %d has degree %d (< 2)", name, i, rp[i + 1] - rp[i]);
+        for (int t = rp[i]; t < rp[i + 1]; ++t) {
+            int j = ci[t];
+            if (j < 0 || j >= n) return fail(SAGMS_EINVAL, "%s: column %d out of range in row %d", name, j, i);
+            if (seen[j]) return fail(SAGMS_EINVAL, "%s: column %d repeated in row %d", name, j, i);
+            seen[j] = 1;
+        }
+        for (int t = rp[i]; t < rp[i + 1]; ++t) seen[ci[t]] = 0;
+    }
+    return SAGMS_OK;
+}
+
+static int build(int32_t m, int32_t n, const std::vector<int>& rp, const std::vector<int>& ci, int32_t m_other,
+                 const std::vector<int>& rpo, const std::vector<int>& cio, sagms_graph* out) {
+    Graph* g = new (std::nothrow) Graph();
+    if (!g) return fail(SAGMS_ENOMEM, "graph allocation failed");
+    g->m = m;
+    g->n = n;
+    g->row_ptr = rp;
+    g->cols = ci;
+    int rc = finish_graph(g, rpo, cio, m_other);
+    if (rc != SAGMS_OK) {
+        delete g;
+        return rc;
+    }
+    *out = reinterpret_cast<sagms_graph>(g);
+    return SAGMS_OK;
+}
+
+// ---- per-device tables ------------------------------------------------
+int device_tables(Graph* g, DeviceTables** out, hipStream_t stream) {
+    int dev = 0;
+    SAGMS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SAGMS_EUNSUPPORTED, "device index %d too large", dev);
+    std::lock_guard<std::mutex> lock(g->mu);
+    DeviceTables* t = &g->dev[dev];
+    if (!t->ready) {
+        size_t ncols = (size_t)g->m * std::max(g->dc_max, 1);
+        std::vector<int32_t> cols(ncols, -1);
+        for (int c = 0; c < g->m; ++c)
+            for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p)
+                cols[(size_t)c * std::max(g->dc_max, 1) + p] = g->cols[g->row_ptr[c] + p];
+        SAGMS_HIP(hipMalloc(&t->cols, std::max<size_t>(ncols, 1) * sizeof(int32_t)));
+        SAGMS_HIP(hipMemcpy(t->cols, cols.data(), ncols * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (g->shape_ok) {
+            SAGMS_HIP(hipMalloc(&t->cn_addr, g->cn_addr_host.size() * sizeof(uint32_t)));
+            SAGMS_HIP(hipMemcpy(t->cn_addr, g->cn_addr_host.data(), g->cn_addr_host.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice));
+            SAGMS_HIP(hipMalloc(&t->vn_addr, g->vn_addr_host.size() * sizeof(uint32_t)));
+            SAGMS_HIP(hipMemcpy(t->vn_addr, g->vn_addr_host.data(), g->vn_addr_host.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice));
+        }
+        if (g->k > 0) {
+            SAGMS_HIP(hipMalloc(&t->logicals, g->logicals.size() * sizeof(uint64_t)));
+            SAGMS_HIP(hipMemcpy(t->logicals, g->logicals.data(), g->logicals.size() * sizeof(uint64_t),
+                                hipMemcpyHostToDevice));
+        }
+        t->ready = true;
+    }
+    (void)stream;
+    *out = t;
+    return SAGMS_OK;
+}
+
+// Gain law of eq. (alphaeff), tabulated over the residual-syndrome weight w
+// in IEEE double and rounded to float (pairs: satisfied, unsatisfied check).
+static std::vector<float> make_gains(const GainKey& key, int m, int entries) {
+    std::vector<float> t(2 * (size_t)entries, 1.0f);
+    for (int w = 0; w <= m && w < entries; ++w) {
+        double gs = 1.0, gu = 1.0;
+        if (key.kind == SAGMS_SMS) {
+            gs = gu = key.a;
+        } else if (key.kind == SAGMS_SAGMS) {
+            double gamma = (double)w / (double)m;
+            double gl = key.amax - (key.amax - key.amin) * gamma;
+            gs = gl;
+            gu = gl * key.eta;
+        }
+        t[2 * (size_t)w] = (float)gs;
+        t[2 * (size_t)w + 1] = (float)gu;
+    }
+    return t;
+}
+
+int gain_table(Graph* g, DeviceTables* t, const GainKey& key, const float** out, hipStream_t stream) {
+    std::lock_guard<std::mutex> lock(g->mu);
+    auto it = t->gains.find(key);
+    if (it != t->gains.end()) {
+        *out = it->second;
+        return SAGMS_OK;
+    }
+    int entries = g->layout.cw + 1;
+    std::vector<float>& host = t->gains_host[key];
+    host = make_gains(key, g->m, entries);
+    float* d = nullptr;
+    SAGMS_HIP(hipMalloc(&d, host.size() * sizeof(float)));
+    SAGMS_HIP(hipMemcpyAsync(d, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, stream));
+    t->gains[key] = d;
+    *out = d;
+    return SAGMS_OK;
+}
+
+}  // namespace sagms
+
+using namespace sagms;
+
+extern "C" {
+
+const char* sagms_last_error(void) { return g_last_error.c_str(); }
+
+int sagms_build_graph(int32_t m, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t m_other,
+                      const int32_t* row_ptr_o, const int32_t* col_idx_o, sagms_graph* out) {
+    if (!out) return fail(SAGMS_EINVAL, "out is null");
+    *out = nullptr;
+    if (m < 1 || n < 1 || n > kMaxN) return fail(SAGMS_EINVAL, "need 1 <= m and 1 <= n <= %d (m=%d n=%d)", kMaxN, m, n);
+    int rc = check_csr(m, n, row_ptr, col_idx, "H", true);
+    if (rc) return rc;
+    std::vector<int> rp(row_ptr, row_ptr + m + 1), ci(col_idx, col_idx + row_ptr[m]);
+    std::vector<int> rpo, cio;
+    if (m_other < 0) return fail(SAGMS_EINVAL, "m_other must be >= 0");
+    if (m_other > 0) {
+        rc = check_csr(m_other, n, row_ptr_o, col_idx_o, "H_other", false);
+        if (rc) return rc;
+        rpo.assign(row_ptr_o, row_ptr_o + m_other + 1);
+        cio.assign(col_idx_o, col_idx_o + row_ptr_o[m_other]);
+    }
+    return build(m, n, rp, ci, m_other, rpo, cio, out);
+}
+
+int sagms_build_gb(int32_t l, const int32_t* a, int32_t wa, const int32_t* b, int32_t wb, sagms_graph* out) {
+    if (!out) return fail(SAGMS_EINVAL, "out is null");
+    *out = nullptr;
+    if (l < 2 || 2 * l > kMaxN) return fail(SAGMS_EINVAL, "circulant size l=%d out of range", l);
+    if (!a || !b || wa < 1 || wb < 1 || wa + wb < 2) return fail(SAGMS_EINVAL, "bad polynomial arguments");
+    for (int t = 0; t < wa; ++t)
+        if (a[t] < 0 || a[t] >= l) return fail(SAGMS_EINVAL, "exponent a[%d]=%d out of range", t, a[t]);
+    for (int t = 0; t < wb; ++t)
+        if (b[t] < 0 || b[t] >= l) return fail(SAGMS_EINVAL, "exponent b[%d]=%d out of range", t, b[t]);
+    for (int s = 0; s < wa; ++s)
+        for (int t = s + 1; t < wa; ++t)
+            if (a[s] == a[t]) return fail(SAGMS_EINVAL, "repeated exponent in a");
+    for (int s = 0; s < wb; ++s)
+        for (int t = s + 1; t < wb; ++t)
+            if (b[s] == b[t]) return fail(SAGMS_EINVAL, "repeated exponent in b");
+    // H_Z = [B^T | A^T]: row c has ones at (c - b_t) mod l and l + (c - a_t) mod l.
+    // Edge positions follow the polynomial terms, so that lanes reading the
+    // same position touch consecutive posteriors (the order does not change
+    // any result: the check update is symmetric in its inputs).
+    std::vector<int> rp(l + 1), ci;
+    for (int c = 0; c < l; ++c) {
+        rp[c] = (int)ci.size();
+        for (int t = 0; t < wb; ++t) ci.push_back(((c - b[t]) % l + l) % l);
+        for (int t = 0; t < wa; ++t) ci.push_back(l + ((c - a[t]) % l + l) % l);
+    }
+    rp[l] = (int)ci.size();
+    // H_X = [A | B]: row c has ones at (c + a_t) mod l and l + (c + b_t) mod l.
+    std::vector<int> rpo(l + 1), cio;
+    for (int c = 0; c < l; ++c) {
+        rpo[c] = (int)cio.size();
+        for (int t = 0; t < wa; ++t) cio.push_back((c + a[t]) % l);
+        for (int t = 0; t < wb; ++t) cio.push_back(l + (c + b[t]) % l);
+    }
+    rpo[l] = (int)cio.size();
+    return build(l, 2 * l, rp, ci, l, rpo, cio, out);
+}
+
+int sagms_graph_info(sagms_graph gh, sagms_graph_info_t* info) {
+    Graph* g = reinterpret_cast<Graph*>(gh);
+    if (!g || !info) return fail(SAGMS_EINVAL, "null argument");
+    info->m = g->m;
+    info->n = g->n;
+    info->n_edges = g->E;
+    info->k = g->have_other ? g->k : -1;
+    info->dc_max = g->dc_max;
+    info->dv_max = g->dv_max;
+    info->words_n = g->wn;
+    info->words_m = g->wm;
+    return SAGMS_OK;
+}
+
+int sagms_graph_rows(sagms_graph gh, uint64_t* rows) {
+    Graph* g = reinterpret_cast<Graph*>(gh);
+    if (!g || !rows) return fail(SAGMS_EINVAL, "null argument");
+    std::memcpy(rows, g->rows_bits.data(), g->rows_bits.size() * sizeof(uint64_t));
+    return SAGMS_OK;
+}
+
+int sagms_graph_logicals(sagms_graph gh, uint64_t* rows) {
+    Graph* g = reinterpret_cast<Graph*>(gh);
+    if (!g || !rows) return fail(SAGMS_EINVAL, "null argument");
+    if (!g->have_other) return fail(SAGMS_EINVAL, "graph has no other matrix");
+    std::memcpy(rows, g->logicals.data(), g->logicals.size() * sizeof(uint64_t));
+    return SAGMS_OK;
+}
+
+int sagms_destroy_graph(sagms_graph gh) {
+    Graph* g = reinterpret_cast<Graph*>(gh);
+    if (!g) return fail(SAGMS_EINVAL, "null graph");
+    int cur = -1;
+    bool have_dev = hipGetDevice(&cur) == hipSuccess;
+    for (int d = 0; d < kMaxDevices; ++d) {
+        DeviceTables& t = g->dev[d];
+        if (!t.ready) continue;
+        if (have_dev) (void)hipSetDevice(d);
+        (void)hipFree(t.cols);
+        (void)hipFree(t.cn_addr);
+        (void)hipFree(t.vn_addr);
+        (void)hipFree(t.logicals);
+        for (auto& kv : t.gains) (void)hipFree(kv.second);
+    }
+    if (have_dev) (void)hipSetDevice(cur);
+    delete g;
+    return SAGMS_OK;
+}
+
+float sagms_prior_llr(double p) {
+    if (!(p > 0.0 && p < 0.75)) return NAN;
+    double q = 2.0 * p / 3.0;
+    return (float)std::log((1.0 - q) / q);
+}
+
+}  // extern "C"

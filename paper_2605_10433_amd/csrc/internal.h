@@ -1,0 +1,138 @@
+// Internal declarations of libsagms (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sagms.h"
+
+namespace sagms {
+
+// ---- errors -----------------------------------------------------------
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+#define SAGMS_HIP(call)                                      \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+    } while (0)
+
+constexpr int kMaxDevices = 64;
+constexpr int kMaxN = 4096;
+
+// ---- decode kernel shapes ---------------------------------------------
+// One wavefront decodes one frame at a time.  Lane l owns checks l + 64 k
+// (k < CPL) and variables l + 64 k (k < VPL).  DC / DV bound the check and
+// variable degrees (shorter rows are padded).
+struct DecodeShape {
+    int dc, dv, cpl, vpl;
+};
+
+// Per-wave LDS layout of the decode kernels, in 32-bit words:
+//   c2v slots  [dc][cw]   slot(c, p) = p * cw + c  (cw = 64 * cpl)
+//   zero       one word holding 0.0f (padding of short variables)
+//   posterior  [64 * vpl] posterior of variable j at post0 + j
+//   padpost    one word holding +inf (padding of short checks)
+//   gains      [2 * (64 * cpl + 1)] pairs (gain satisfied, gain unsatisfied)
+//              indexed by the residual-syndrome weight w
+struct DecodeLayout {
+    int cw, zero, post0, padpost, gain0, words;
+};
+
+struct GainKey {
+    int kind;
+    double a, amin, amax, eta;
+    bool operator<(const GainKey& o) const {
+        return std::tie(kind, a, amin, amax, eta) < std::tie(o.kind, o.a, o.amin, o.amax, o.eta);
+    }
+};
+
+struct DeviceTables {
+    bool ready = false;
+    uint32_t* cn_addr = nullptr;   // [cpl * dc][64] LDS word index of the posterior read at (check, pos)
+    uint32_t* vn_addr = nullptr;   // [vpl * dv][64] LDS word index of the c2v slot read at (var, rank)
+    int32_t* cols = nullptr;       // [m][dc_max] column of (check, pos), -1 padded (sampler)
+    uint64_t* logicals = nullptr;  // [k][words_n]
+    std::map<GainKey, float*> gains;
+    std::map<GainKey, std::vector<float>> gains_host;  // kept alive for async uploads
+};
+
+struct Graph {
+    int m = 0, n = 0, E = 0, dc_max = 0, dv_max = 0, k = -1, wn = 0, wm = 0;
+    // decoding matrix H: row i has columns cols[row_ptr[i] .. row_ptr[i+1]-1] in
+    // the order used as the check's edge positions
+    std::vector<int> row_ptr, cols;
+    std::vector<uint64_t> rows_bits;   // [m][wn]
+    std::vector<uint64_t> logicals;    // [k][wn]
+    bool have_other = false;
+    bool shape_ok = false;
+    DecodeShape shape{};
+    DecodeLayout layout{};
+    std::vector<uint32_t> cn_addr_host, vn_addr_host;
+    std::mutex mu;
+    DeviceTables dev[kMaxDevices];
+};
+
+// GF(2) helpers (graph.cpp)
+int gf2_rank(std::vector<uint64_t> rows, int nrows, int wn);
+
+// Returns the device tables of g on the current device, creating them once.
+int device_tables(Graph* g, DeviceTables** out, hipStream_t stream);
+// Device gain table for a decoder configuration (created once per device).
+int gain_table(Graph* g, DeviceTables* t, const GainKey& key, const float** out, hipStream_t stream);
+
+// Shape selection for the decode kernels.
+bool pick_shape(int m, int n, int dc, int dv, DecodeShape* out);
+DecodeLayout make_layout(const DecodeShape& s);
+
+// Kernel launchers (one translation unit each).
+struct DecodeArgs {
+    const uint64_t* synd;
+    const float* llr0;
+    const float* gains;
+    const uint32_t* cn_addr;
+    const uint32_t* vn_addr;
+    uint64_t* ehat;
+    int32_t* iters;
+    uint8_t* conv;
+    float* post;  // optional soft output [nframes][n]
+    int64_t nframes;
+    int m, n, wm, wn, lmax, frames_per_wave;
+    DecodeLayout L;
+};
+int launch_decode(const DecodeShape& s, bool bp, const DecodeArgs& a, int waves_per_block, hipStream_t st);
+
+struct SampleArgs {
+    const int32_t* cols;
+    uint64_t* ex;
+    uint64_t* ez;
+    uint64_t* synd;
+    uint64_t seed;
+    uint64_t frame0;
+    int64_t nframes;
+    uint32_t stream_id;
+    uint32_t tx, ty, tz;
+    int m, n, dc, wn, wm, frames_per_wave;
+};
+int launch_sample(const SampleArgs& a, hipStream_t st);
+
+struct JudgeArgs {
+    const uint64_t* ex;
+    const uint64_t* ehat;
+    const uint8_t* conv;
+    const int32_t* iters;
+    const uint64_t* logicals;
+    uint8_t* fail;
+    uint64_t* counters;
+    int64_t nframes;
+    int k, wn;
+};
+int launch_judge(const JudgeArgs& a, hipStream_t st);
+
+}  // namespace sagms

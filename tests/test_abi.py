@@ -1,0 +1,138 @@
+"""Host-side checks of libsagms (no GPU needed).
+
+The library loads and exports every function include/sagms.h declares; the
+host graph builder agrees with the oracle (matrices, k, logical basis); the
+argument checks of the device entry points reject bad input before any
+device work.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2605_10433_amd as sagms
+import workloads
+from oracle import channel, codes, gf2
+
+
+def test_exports_every_declared_symbol():
+    names = sagms.header_functions()
+    assert len(names) >= 12
+    L = sagms.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("name", ["G63", "G127", "G255w3", "G255w4", "G511w5"])
+def test_gb_graph_matches_oracle(name):
+    l, a, b = workloads.code(name)
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    k = codes.dimension(hx, hz)
+    assert (g.m, g.n, g.n_edges) == (l, 2 * l, int(hz.sum()))
+    assert (g.dc_max, g.dv_max) == (int(hz.sum(1).max()), int(hz.sum(0).max()))
+    assert g.k == k == workloads.CODES[name]["k"]
+    assert (g.words_n, g.words_m) == ((2 * l + 63) // 64, (l + 63) // 64)
+    assert (channel.unpack(g.rows(), g.n) == hz).all()
+    lz = channel.unpack(g.logicals(), g.n)
+    assert lz.shape == (k, g.n)
+    assert not gf2.matvec(hx, lz).any()                              # in ker H_X
+    assert gf2.rank(np.vstack([hz, lz])) == gf2.rank(hz) + k         # independent mod rowspace H_Z
+
+
+@pytest.mark.parametrize("code", [dict(l=7, a=(0, 1), b=(0, 2)), dict(l=7, a=(0, 1, 3), b=(0, 2, 6))])
+def test_small_gb_codes(code):
+    g = sagms.Graph.gb(code["l"], code["a"], code["b"])
+    hx, hz = codes.gb_matrices(**code)
+    assert g.k == codes.dimension(hx, hz)
+    assert (channel.unpack(g.rows(), g.n) == hz).all()
+
+
+def test_build_graph_from_dense_matches_gb():
+    hx, hz = codes.gb_matrices(**codes.G63)
+    g = sagms.Graph.from_dense(hz, hx)
+    assert g.k == 28 and (channel.unpack(g.rows(), 126) == hz).all()
+    g2 = sagms.Graph.from_dense(hz)
+    assert g2.k == -1
+    with pytest.raises(sagms.SagmsError):
+        g2.logicals()
+
+
+def _csr_call(m, n, rp, ci, mo=0, rpo=None, cio=None):
+    rp = np.asarray(rp, dtype=np.int32)
+    ci = np.asarray(ci, dtype=np.int32)
+    args = [m, n, rp.ctypes.data, ci.ctypes.data, mo]
+    if mo:
+        rpo = np.asarray(rpo, dtype=np.int32)
+        cio = np.asarray(cio, dtype=np.int32)
+        args += [rpo.ctypes.data, cio.ctypes.data]
+    else:
+        args += [None, None]
+    h = ctypes.c_void_p()
+    rc = sagms.lib().sagms_build_graph(*args, ctypes.byref(h))
+    if rc == 0:
+        sagms.lib().sagms_destroy_graph(h)
+    return rc
+
+
+def test_build_graph_rejects_bad_input():
+    assert _csr_call(2, 4, [0, 2, 4], [0, 1, 2, 3]) == sagms.OK
+    assert _csr_call(2, 4, [0, 1, 3], [0, 1, 2]) == sagms.EINVAL          # check of degree 1
+    assert _csr_call(2, 4, [0, 2, 4], [0, 4, 2, 3]) == sagms.EINVAL       # column out of range
+    assert _csr_call(2, 4, [0, 2, 4], [1, 1, 2, 3]) == sagms.EINVAL       # repeated column
+    assert _csr_call(2, 4, [1, 2, 4], [0, 1, 2, 3]) == sagms.EINVAL       # row_ptr[0] != 0
+    assert _csr_call(0, 4, [0], []) == sagms.EINVAL
+    assert _csr_call(1, 5000, [0, 2], [0, 1]) == sagms.EINVAL             # n too large
+    # anticommuting partner matrix
+    assert _csr_call(1, 4, [0, 2], [0, 1], 1, [0, 2], [1, 2]) == sagms.EINVAL
+    assert _csr_call(1, 4, [0, 2], [0, 1], 1, [0, 2], [0, 1]) == sagms.OK
+    with pytest.raises(sagms.SagmsError):
+        sagms.Graph.gb(7, [0, 0], [1, 2])                                  # repeated exponent
+    with pytest.raises(sagms.SagmsError):
+        sagms.Graph.gb(7, [0, 9], [1, 2])                                  # exponent out of range
+
+
+def _decode_rc(g, cfg):
+    return sagms.lib().sagms_decode(g._h, None, None, ctypes.byref(cfg), 4, None, None, None, None)
+
+
+def test_decoder_config_checks_before_device_work():
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    D = sagms.decoder_config
+    assert _decode_rc(g, D("sagms", alpha_max=0.6, eta=2.0)) == sagms.EINVAL      # alpha_max * eta > 1
+    assert _decode_rc(g, D("sagms", alpha_min=0.0)) == sagms.EINVAL
+    assert _decode_rc(g, D("sagms", eta=0.9)) == sagms.EINVAL
+    assert _decode_rc(g, D("sms", alpha=1.5)) == sagms.EINVAL
+    assert _decode_rc(g, D("ms", lmax=0)) == sagms.EINVAL
+    bad = D("ms")
+    bad.kind = 7
+    assert _decode_rc(g, bad) == sagms.EINVAL
+    sched = D("ms")
+    sched.schedule = 1
+    assert _decode_rc(g, sched) == sagms.EUNSUPPORTED
+    prec = D("ms")
+    prec.msg_precision = 3
+    assert _decode_rc(g, prec) == sagms.EUNSUPPORTED
+    # a valid configuration with zero frames is a no-op that touches no device
+    ok = D("sagms")
+    assert sagms.lib().sagms_decode(g._h, None, None, ctypes.byref(ok), 0, None, None, None, None) == sagms.OK
+    assert "exceeds" in (_decode_rc(g, D("sagms", alpha_max=0.6, eta=2.0)) and
+                         sagms.lib().sagms_last_error().decode())
+
+
+def test_gen_errors_and_judge_argument_checks():
+    L = sagms.lib()
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    assert L.sagms_gen_errors(g._h, 1, 0, 0, 4, 1.0, None, None, None, None) == sagms.EINVAL
+    assert L.sagms_gen_errors(g._h, 1, 0, 0, -1, 0.1, None, None, None, None) == sagms.EINVAL
+    assert L.sagms_gen_errors(g._h, 1, 0, 0, 0, 0.1, None, None, None, None) == sagms.OK
+    assert L.sagms_gen_errors(g._h, 1, 0, 0, 4, 0.1, None, None, None, None) == sagms.EINVAL  # null buffers
+    assert L.sagms_gen_errors(None, 1, 0, 0, 4, 0.1, None, None, None, None) == sagms.EINVAL
+    g2 = sagms.Graph.from_dense(codes.gb_matrices(**codes.G63)[1])
+    assert L.sagms_judge(g2._h, None, None, None, None, 4, None, None, None) == sagms.EINVAL   # no H_other
+
+
+@pytest.mark.parametrize("p", workloads.P_GRID + [0.001, 0.3])
+def test_prior_llr_matches_oracle(p):
+    assert sagms.prior_llr(p) == np.float32(channel.prior_llr(p))
+    assert np.isnan(sagms.prior_llr(0.0)) and np.isnan(sagms.prior_llr(0.8))

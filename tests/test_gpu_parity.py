@@ -1,0 +1,328 @@
+"""GPU parity: libsagms (through its C ABI) against the CPU oracle.
+
+Bar: bit-exact error samples, syndromes, hard decisions, round counts,
+convergence flags, judge verdicts and counters; the FP32 posteriors are
+bit-identical to the oracle's FP32 mode (same operation order) and within
+1e-5 relative (floor L0) of its FP64 mode on frames whose FP64 trajectory
+keeps away from decision ties.  BP (transcendental CN) is compared by
+tolerance and agreement fraction.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import paper_2605_10433_amd as sagms  # noqa: E402
+import workloads  # noqa: E402
+from oracle import channel, codes, decoders, judge, stats  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SMALL = {"L7a": (7, [0, 1], [0, 2]), "L7b": (7, [0, 1, 3], [0, 2, 6])}
+
+
+def code_of(name):
+    return SMALL[name] if name in SMALL else workloads.code(name)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def say(*args):
+    print(*args, flush=True)
+
+
+def gpu_decode(g, synd_bits, llr, cfg, dev, soft=True):
+    f = synd_bits.shape[0]
+    synd = torch.from_numpy(channel.pack(synd_bits).view(np.int64)).to(dev) if f else \
+        torch.empty((0, g.words_m), dtype=torch.int64, device=dev)
+    out = sagms.frame_buffers(g, f, device=dev)
+    post = torch.empty((f, g.n), dtype=torch.float32, device=dev)
+    llr_dev = torch.from_numpy(np.asarray(llr, dtype=np.float32)).to(dev)
+    if soft:
+        sagms.decode_soft(g, synd, llr_dev, cfg, out["ehat"], out["iters"], out["converged"], post)
+    else:
+        sagms.decode(g, synd, llr_dev, cfg, out["ehat"], out["iters"], out["converged"])
+    torch.cuda.synchronize()
+    return (channel.unpack(u64(out["ehat"]), g.n), out["iters"].cpu().numpy(),
+            out["converged"].cpu().numpy().astype(bool), post.cpu().numpy())
+
+
+def params(kind, lmax, **kw):
+    return decoders.DecoderParams(kind=kind, lmax=lmax, **kw), sagms.decoder_config(kind, lmax=lmax, **kw)
+
+
+# ------------------------------------------------------------------ sampler
+@pytest.mark.parametrize("name", ["L7a", "G63", "G127", "G255w3", "G511w5"])
+@pytest.mark.parametrize("p", [0.0, 0.05, 0.3])
+def test_sampler_bit_exact(dev, name, p):
+    l, a, b = code_of(name)
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    for seed, stream_id, frame0, nf in ((1, 0, 0, 333), (0xDEADBEEF12345, 7, (1 << 32) - 100, 257)):
+        say("sampler", name, p, seed, stream_id, frame0, nf)
+        buf = sagms.frame_buffers(g, nf, device=dev)
+        sagms.gen_errors(g, seed, stream_id, frame0, nf, p, buf["ex"], buf["ez"], buf["synd"])
+        torch.cuda.synchronize()
+        ex, ez = channel.sample_paulis(seed, stream_id, frame0, nf, g.n, p)
+        assert (u64(buf["ex"]) == channel.pack(ex)).all()
+        assert (u64(buf["ez"]) == channel.pack(ez)).all()
+        assert (u64(buf["synd"]) == channel.pack(channel.syndrome(hz, ex))).all()
+
+
+def test_sampler_without_z_plane_and_empty(dev):
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    buf = sagms.frame_buffers(g, 100, device=dev, with_ez=False)
+    sagms.gen_errors(g, 3, 2, 5, 100, 0.07, buf["ex"], None, buf["synd"])
+    sagms.gen_errors(g, 3, 2, 5, 0, 0.07, buf["ex"][:0], None, buf["synd"][:0])
+    torch.cuda.synchronize()
+    ex, _ = channel.sample_paulis(3, 2, 5, 100, 126, 0.07)
+    assert (u64(buf["ex"]) == channel.pack(ex)).all()
+
+
+# ------------------------------------------------------------------ decoder
+DECODERS = [("ms", {}), ("sms", dict(alpha=0.5)), ("sms", dict(alpha=0.625)), ("sms", dict(alpha=0.75)),
+            ("sms", dict(alpha=0.875)), ("sagms", {})]
+
+
+@pytest.mark.parametrize("kind,kw", DECODERS)
+@pytest.mark.parametrize("p", [0.02, 0.05, 0.1])
+def test_decode_bit_exact_g63(dev, kind, kw, p):
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    nf = 1200
+    ex, _ = channel.sample_paulis(1, workloads.stream_of(p), 0, nf, g.n, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    prm, cfg = params(kind, 100, **kw)
+    say("decode G63", kind, kw, p, nf)
+    e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    assert (it == r.iters).all()
+    assert (cv == r.converged).all()
+    assert (e == r.ehat).all()
+    assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("name,nf", [("L7a", 300), ("L7b", 300), ("G127", 400), ("G255w3", 200),
+                                     ("G255w4", 200), ("G511w5", 60)])
+@pytest.mark.parametrize("kind", ["ms", "sms", "sagms"])
+def test_decode_bit_exact_other_codes(dev, name, nf, kind):
+    l, a, b = code_of(name)
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    p = 0.04
+    ex, _ = channel.sample_paulis(5, 3, 0, nf, g.n, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    prm, cfg = params(kind, 60, **({"alpha": 0.75} if kind == "sms" else {}))
+    say("decode", name, kind, nf)
+    e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
+    assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("lmax", [1, 2, 7])
+@pytest.mark.parametrize("kind", ["ms", "sagms"])
+def test_decode_arbitrary_syndromes_and_priors(dev, lmax, kind):
+    """All-zero / all-one / random syndromes, non-uniform, negative and -0.0 priors."""
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    s = workloads.random_syndromes(g.m, 300, seed=lmax)
+    rng = np.random.default_rng(17)
+    llr = rng.uniform(-1.0, 5.0, size=g.n).astype(np.float32)
+    llr[3] = -0.0
+    llr[4] = 0.0
+    prm, cfg = params(kind, lmax)
+    say("decode arbitrary", kind, lmax)
+    e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
+    assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
+    assert (it[~cv] == lmax).all()
+
+
+def test_decode_zero_noise_and_tiny_batches(dev):
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    hz = codes.gb_matrices(*workloads.code("G63"))[1]
+    llr = np.full(g.n, channel.prior_llr(0.05), dtype=np.float32)
+    cfg = sagms.decoder_config("sagms")
+    for nf in (1, 2, 3, 5, 63, 65):
+        s = np.zeros((nf, g.m), dtype=np.uint8)
+        e, it, cv, _ = gpu_decode(g, s, llr, cfg, dev)
+        assert not e.any() and (it == 0).all() and cv.all()
+    s = workloads.random_syndromes(g.m, 5, seed=9, density=0.05)
+    e, it, cv, _ = gpu_decode(g, s, llr, cfg, dev, soft=False)
+    r = decoders.decode(decoders.TannerGraph(hz), s, llr, decoders.DecoderParams(kind="sagms"), "fp32")
+    assert (it == r.iters).all() and (e == r.ehat).all()
+
+
+def test_decode_from_csr_graph_with_irregular_degrees(dev):
+    """A non-GB graph with uneven check and variable degrees (padded shapes)."""
+    rng = np.random.default_rng(4)
+    m, n = 40, 90
+    h = np.zeros((m, n), dtype=np.uint8)
+    for i in range(m):
+        h[i, rng.choice(n, size=int(rng.integers(2, 11)), replace=False)] = 1
+    g = sagms.Graph.from_dense(h)
+    s = workloads.random_syndromes(m, 400, seed=5, density=0.2)
+    llr = rng.uniform(0.5, 4.0, size=n).astype(np.float32)
+    for kind in ("ms", "sagms"):
+        prm, cfg = params(kind, 25)
+        say("decode csr", kind, g.dc_max, g.dv_max)
+        e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+        r = decoders.decode(decoders.TannerGraph(h), s, llr, prm, "fp32")
+        assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
+        assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
+
+
+def test_fp32_posteriors_within_tolerance_of_fp64(dev):
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    p = 0.05
+    ex, _ = channel.sample_paulis(1, 4, 0, 1500, g.n, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    prm, cfg = params("sagms", 100)
+    e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+    r64 = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp64")
+    same = (it == r64.iters) & (e == r64.ehat).all(axis=1)
+    assert same.mean() > 0.99
+    L0 = float(llr[0])
+    tol = 1e-5 * np.maximum(np.abs(r64.posterior[same]), L0)
+    assert (np.abs(post[same] - r64.posterior[same]) <= tol).all()
+
+
+def test_bp_against_oracle(dev):
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    p = 0.05
+    nf = 1000
+    ex, _ = channel.sample_paulis(1, 4, 0, nf, g.n, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    prm, cfg = params("bp", 100)
+    say("decode bp")
+    e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    agree = (it == r.iters) & (e == r.ehat).all(axis=1)
+    assert agree.mean() > 0.97
+    tol = 1e-4 * np.maximum(np.abs(r.posterior[agree]), float(llr[0]))
+    close = (np.abs(post[agree] - r.posterior[agree]) <= tol).all(axis=1)
+    assert close.mean() > 0.97
+    resid = s ^ channel.syndrome(hz, e)
+    assert not resid[cv].any()
+
+
+# ------------------------------------------------------------------ judge
+def test_judge_matches_oracle_rank_test(dev):
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    nf, p = 3000, 0.08
+    buf = sagms.frame_buffers(g, nf, device=dev)
+    llr = torch.full((g.n,), float(np.float32(channel.prior_llr(p))), device=dev)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    sagms.gen_errors(g, 2, 6, 0, nf, p, buf["ex"], buf["ez"], buf["synd"])
+    sagms.decode(g, buf["synd"], llr, sagms.decoder_config("ms", lmax=30), buf["ehat"], buf["iters"], buf["converged"])
+    sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters, fail=buf["fail"])
+    torch.cuda.synchronize()
+    ex = channel.unpack(u64(buf["ex"]), g.n)
+    eh = channel.unpack(u64(buf["ehat"]), g.n)
+    cv = buf["converged"].cpu().numpy().astype(bool)
+    fail = buf["fail"].cpu().numpy().astype(bool)
+    ref = judge.judge_rank(hx, ex[:600], eh[:600], cv[:600])
+    assert (fail[:600] == ref).all()
+    assert (fail == judge.judge_logical(codes.logical_basis(hz, hx), ex, eh, cv)).all()
+    c = counters.cpu().numpy()
+    assert c[0] == fail.sum() and c[1] == buf["iters"].cpu().numpy().sum()
+    # converged but logically wrong frames exist at this noise level
+    assert (fail & cv).any()
+
+
+# ----------------------------------------------- full size, bench launch shape
+def test_full_size_sampled_frames(dev):
+    """2^20 frames at p = 0.05 (the timed workload), SAGMS, l_max = 100:
+    sampled frames recomputed one by one by the oracle, counters checked
+    against the per-frame verdicts, FER inside the Wilson interval of the
+    oracle's own estimate on an independent prefix."""
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    nf, p = workloads.SWEEP_FRAMES, 0.05
+    st = workloads.stream_of(p)
+    buf = sagms.frame_buffers(g, nf, device=dev)
+    llr = torch.full((g.n,), float(np.float32(channel.prior_llr(p))), device=dev)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    cfg = sagms.decoder_config("sagms", lmax=100)
+    say("full size", nf)
+    sagms.gen_errors(g, workloads.SWEEP_SEED, st, 0, nf, p, buf["ex"], buf["ez"], buf["synd"])
+    sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
+    sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters, fail=buf["fail"])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(123)
+    idx = np.sort(rng.choice(nf, size=256, replace=False))
+    idx[-1] = nf - 1
+    ex_all, synd_all = u64(buf["ex"]), u64(buf["synd"])
+    eh_all, it_all = u64(buf["ehat"]), buf["iters"].cpu().numpy()
+    cv_all, fail_all = buf["converged"].cpu().numpy(), buf["fail"].cpu().numpy()
+    tg = decoders.TannerGraph(hz)
+    lz = codes.logical_basis(hz, hx)
+    llr_np = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    exs = np.vstack([channel.sample_paulis(workloads.SWEEP_SEED, st, int(f), 1, g.n, p)[0] for f in idx])
+    s = channel.syndrome(hz, exs)
+    assert (channel.pack(exs) == ex_all[idx]).all() and (channel.pack(s) == synd_all[idx]).all()
+    r = decoders.decode(tg, s, llr_np, decoders.DecoderParams(kind="sagms", lmax=100), "fp32")
+    assert (channel.pack(r.ehat) == eh_all[idx]).all()
+    assert (r.iters == it_all[idx]).all() and (r.converged == cv_all[idx]).all()
+    assert (judge.judge_logical(lz, exs, r.ehat, r.converged) == fail_all[idx]).all()
+    c = counters.cpu().numpy()
+    assert c[0] == fail_all.sum() and c[1] == it_all.sum()
+    # oracle FER on its own prefix; the two estimates' Wilson intervals overlap
+    pre = 4000
+    ex0, _ = channel.sample_paulis(workloads.SWEEP_SEED, st, 0, pre, g.n, p)
+    r0 = decoders.decode(tg, channel.syndrome(hz, ex0), llr_np, decoders.DecoderParams(kind="sagms", lmax=100), "fp64")
+    f0 = int(judge.judge_logical(lz, ex0, r0.ehat, r0.converged).sum())
+    lo0, hi0 = stats.wilson(f0, pre)
+    lo1, hi1 = stats.wilson(int(c[0]), nf)
+    assert lo0 <= hi1 and lo1 <= hi0
+
+
+def test_determinism_split_and_streams(dev):
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    nf, p = 5000, 0.06
+    buf = sagms.frame_buffers(g, nf, device=dev)
+    sagms.gen_errors(g, 9, 1, 0, nf, p, buf["ex"], buf["ez"], buf["synd"])
+    llr = torch.full((g.n,), float(np.float32(channel.prior_llr(p))), device=dev)
+    cfg = sagms.decoder_config("sagms", lmax=100)
+    sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
+    ref = [buf[k].clone() for k in ("ehat", "iters", "converged")]
+    # again, and split in two calls on two other streams
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    k = 1777
+    with torch.cuda.stream(s1):
+        sagms.decode(g, buf["synd"][:k], llr, cfg, buf["ehat"][:k], buf["iters"][:k], buf["converged"][:k])
+    with torch.cuda.stream(s2):
+        sagms.decode(g, buf["synd"][k:], llr, cfg, buf["ehat"][k:], buf["iters"][k:], buf["converged"][k:])
+    torch.cuda.synchronize()
+    for key, r in zip(("ehat", "iters", "converged"), ref):
+        assert torch.equal(buf[key], r), key
+    # a frame range generated separately equals the slice of the whole batch
+    part = sagms.frame_buffers(g, 100, device=dev)
+    sagms.gen_errors(g, 9, 1, 2500, 100, p, part["ex"], part["ez"], part["synd"])
+    torch.cuda.synchronize()
+    assert torch.equal(part["ex"], buf["ex"][2500:2600]) and torch.equal(part["synd"], buf["synd"][2500:2600])

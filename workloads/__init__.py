@@ -1,0 +1,50 @@
+"""Workload definitions and seeded input generators shared by the tests,
+the bench and the oracle side of the parity checks.
+
+Holds none of the decoding method's arithmetic: only code exponents (read
+from codes.json, written by make_codes.py with the oracle), noise grids,
+seeds / Philox stream assignment, and NumPy-seeded arbitrary syndromes for
+edge-case decoding inputs.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(_HERE, "codes.json")) as _fh:
+    CODES = json.load(_fh)
+
+# The l = 63 sweep: 2^20 frames per point over p = 0.02 .. 0.10, l_max = 100.
+P_GRID = [0.02, 0.03, 0.04, 0.05, 0.06, 0.07, 0.08, 0.09, 0.10]
+SWEEP_FRAMES = 1 << 20
+SWEEP_LMAX = 100
+SWEEP_SEED = 1
+SMS_ALPHAS = [0.5, 0.625, 0.75, 0.875]
+SAGMS_PARAMS = dict(alpha_min=0.30, alpha_max=0.50, eta=1.10)   # Section V setup
+
+# The CPU calibration case: l = 63, p = 0.05, seed 1, stream 0, 10^4 frames, l_max = 50.
+CALIB = dict(code="G63", p=0.05, seed=1, stream=0, frames=10_000, lmax=50)
+
+
+def stream_of(p: float) -> int:
+    """Philox stream of a sweep point: the index of p in the grid."""
+    return P_GRID.index(p)
+
+
+def code(name: str) -> tuple[int, list[int], list[int]]:
+    c = CODES[name]
+    return c["l"], list(c["a"]), list(c["b"])
+
+
+def random_syndromes(m: int, nframes: int, seed: int, density: float = 0.5) -> np.ndarray:
+    """Arbitrary syndrome bits [nframes, m] (uint8), not necessarily reachable by
+    low-weight errors; frame 0 is all zero and frame 1 all one when nframes >= 2."""
+    rng = np.random.default_rng(seed)
+    s = (rng.random((nframes, m)) < density).astype(np.uint8)
+    if nframes >= 2:
+        s[0] = 0
+        s[1] = 1
+    return s
