@@ -2,10 +2,12 @@
 
 Bar: bit-exact error samples, syndromes, hard decisions, round counts,
 convergence flags, judge verdicts and counters; the FP32 posteriors are
-bit-identical to the oracle's FP32 mode (same operation order) and within
-1e-5 relative (floor L0) of its FP64 mode on frames whose FP64 trajectory
-keeps away from decision ties.  BP (transcendental CN) is compared by
-tolerance and agreement fraction.
+bit-identical to the oracle's FP32 mode (same operation order).  Against
+the FP64 mode: over the first 10 rounds, posteriors within 1e-5 relative
+(floor L0) on frames whose FP64 trajectory keeps away from decision ties
+(2e-4 for SMS with alpha >= 0.75, whose round-to-round error gain is >= 3);
+at full length the FER of each lies in the other's Wilson interval.  BP
+(transcendental CN) is compared by tolerance and agreement fraction.
 """
 import numpy as np
 import pytest
@@ -186,22 +188,90 @@ def test_decode_from_csr_graph_with_irregular_degrees(dev):
         assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
 
 
-def test_fp32_posteriors_within_tolerance_of_fp64(dev):
+def tie_flags(trace, nframes, tau):
+    """Frames whose FP64 trajectory brings a posterior or a v2c message within
+    tau of zero (a sign / hard-decision tie) in any recorded round."""
+    near = np.zeros(nframes, dtype=bool)
+    for rd in trace:
+        near[rd["frames"]] |= (np.abs(rd["post"]).min(axis=1) <= tau) | (np.abs(rd["v2c"]).min(axis=1) <= tau)
+    return near
+
+
+# Relative message tolerance against FP64 (floor L0) over the first 10
+# rounds.  Each round adds a handful of FP32 roundings (gain product,
+# d_v posterior additions, one subtraction: about 7 * 2^-24 relative); a
+# round multiplies an earlier error by at most gain * (d_v - 1), which stays
+# <= 2.5 for SAGMS (gain <= 0.55) and SMS with alpha <= 0.625, and is 3 or
+# 3.5 for SMS with alpha = 0.75 / 0.875, whose FP32 and FP64 trajectories
+# separate geometrically (the oracle's own FP32 mode shows the same drift).
+MSG_TOL = {("sagms", None): 1e-5, ("ms", None): 1e-5, ("sms", 0.5): 1e-5, ("sms", 0.625): 1e-5,
+           ("sms", 0.75): 2e-4, ("sms", 0.875): 2e-4}
+
+
+@pytest.mark.parametrize("kind,kw", DECODERS)
+@pytest.mark.parametrize("p", [0.02, 0.05, 0.1])
+def test_fp32_messages_within_tolerance_of_fp64(dev, kind, kw, p):
+    """Posteriors after l = 1..10 rounds against the FP64 oracle, on frames
+    whose FP64 trajectory stays outside the tie band 1e-4 L0; hard decisions
+    and round counts of those frames are identical."""
     l, a, b = workloads.code("G63")
     g = sagms.Graph.gb(l, a, b)
     hx, hz = codes.gb_matrices(l, a, b)
-    p = 0.05
-    ex, _ = channel.sample_paulis(1, 4, 0, 1500, g.n, p)
+    nf = 600
+    ex, _ = channel.sample_paulis(1, workloads.stream_of(p), 0, nf, g.n, p)
     s = channel.syndrome(hz, ex)
     llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
-    prm, cfg = params("sagms", 100)
-    e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
-    r64 = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp64")
-    same = (it == r64.iters) & (e == r64.ehat).all(axis=1)
-    assert same.mean() > 0.99
     L0 = float(llr[0])
-    tol = 1e-5 * np.maximum(np.abs(r64.posterior[same]), L0)
-    assert (np.abs(post[same] - r64.posterior[same]) <= tol).all()
+    tol = MSG_TOL[(kind, kw.get("alpha"))]
+    tg = decoders.TannerGraph(hz)
+    checked = 0
+    for lmax in (1, 2, 3, 5, 7, 10):
+        prm, cfg = params(kind, lmax, **kw)
+        say("fp64 tolerance", kind, kw, p, lmax)
+        e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+        r64 = decoders.decode(tg, s, llr, prm, "fp64", trace=True)
+        ok = ~tie_flags(r64.trace, nf, 1e-4 * L0)
+        assert (it[ok] == r64.iters[ok]).all() and (e[ok] == r64.ehat[ok]).all()
+        err = np.abs(post[ok].astype(np.float64) - r64.posterior[ok]) / np.maximum(np.abs(r64.posterior[ok]), L0)
+        assert (err <= tol).all(), (lmax, float(err.max()))
+        checked += int(ok.sum())
+    # with a dyadic gain (MS: 1, SMS: 0.5) every message is an exact dyadic
+    # combination of a uniform L0, so exact zeros (ties) occur in most frames
+    dyadic = kind == "ms" or kw.get("alpha") == 0.5
+    assert checked > (0 if dyadic else 0.5 * 6 * nf)
+
+
+@pytest.mark.parametrize("kind,kw", DECODERS)
+def test_fer_matches_fp64_oracle(dev, kind, kw):
+    """Full-length decoding (l_max = 100): the GPU FER and the FER of the FP64
+    oracle (fed the FP64 prior) on the same frames each lie in the other's
+    95 % Wilson interval; the fraction of frames whose hard decision
+    differs is small."""
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    p, nf = 0.05, 3000
+    ex, _ = channel.sample_paulis(1, workloads.stream_of(p), 0, nf, g.n, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    prm, cfg = params(kind, 100, **kw)
+    say("fer vs fp64", kind, kw)
+    e, it, cv, _ = gpu_decode(g, s, llr, cfg, dev, soft=False)
+    llr64 = np.full(g.n, channel.prior_llr(p))
+    r64 = decoders.decode(decoders.TannerGraph(hz), s, llr64, prm, "fp64")
+    lz = codes.logical_basis(hz, hx)
+    f_gpu = int(judge.judge_logical(lz, ex, e, cv).sum())
+    f_64 = int(judge.judge_logical(lz, ex, r64.ehat, r64.converged).sum())
+    lo_g, hi_g = stats.wilson(f_gpu, nf)
+    lo_o, hi_o = stats.wilson(f_64, nf)
+    assert lo_o <= f_gpu / nf <= hi_o and lo_g <= f_64 / nf <= hi_g
+    differ = (e != r64.ehat).any(axis=1)
+    both = cv & r64.converged
+    say("FER gpu %.4f fp64 %.4f, HD-disagreeing frames %.4f (%.4f of frames converged in both)"
+        % (f_gpu / nf, f_64 / nf, differ.mean(), differ[both].mean()))
+    # a frame that oscillates until l_max ends in an arbitrary state in either
+    # precision; frames that converge in both agree almost always
+    assert differ[both].mean() < (0.05 if kind == "ms" else 0.01)
 
 
 def test_bp_against_oracle(dev):

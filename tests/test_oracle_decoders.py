@@ -285,27 +285,29 @@ def test_gain_never_exceeds_one():
         DecoderParams(kind="sagms", alpha_max=0.6, eta=2.0).validate()
 
 
-def test_fp32_messages_track_fp64(g63_batch):
-    """FP32 messages stay within 1e-5 relative of FP64 while trajectories agree."""
+@pytest.mark.parametrize("kind,kw,tol", [("sagms", {}, 1e-5), ("sms", dict(alpha=0.625), 1e-5),
+                                         ("ms", {}, 1e-5), ("sms", dict(alpha=0.875), 2e-4)])
+def test_fp32_messages_track_fp64(g63_batch, kind, kw, tol):
+    """Over the first 10 rounds, FP32 messages stay within tol (relative,
+    floor L0) of FP64 on frames whose FP64 trajectory avoids the tie band
+    1e-4 L0; tol follows the per-round error gain gain * (d_v - 1)."""
     g, hz, s, llr = g63_batch
-    prm = DecoderParams(kind="sagms", lmax=12)
-    a = decoders.decode(g, s[:200], llr, prm, "fp64", early_exit=False, trace=True)
-    b = decoders.decode(g, s[:200], llr, prm, "fp32", early_exit=False, trace=True)
+    prm = DecoderParams(kind=kind, lmax=10, **kw)
+    a = decoders.decode(g, s[:300], llr, prm, "fp64", early_exit=False, trace=True)
+    b = decoders.decode(g, s[:300], llr, prm, "fp32", early_exit=False, trace=True)
     L0 = llr[0]
-    same = np.ones(200, dtype=bool)
-    checked = 0
+    near = np.zeros(300, dtype=bool)
+    for ra in a.trace:
+        near |= (np.abs(ra["post"]).min(axis=1) <= 1e-4 * L0) | (np.abs(ra["v2c"]).min(axis=1) <= 1e-4 * L0)
+    ok = ~near
+    # min-sum posteriors are integer combinations of a uniform L0, so MS frames
+    # meet exact zeros (ties) often; the other decoders rarely do
+    assert ok.sum() >= (10 if kind == "ms" else 100)
     for ra, rb in zip(a.trace, b.trace):
-        same &= (ra["post"] < 0).__eq__(rb["post"] < 0).all(axis=1)
-        # compare only frames whose FP64 trajectory keeps away from sign ties
-        safe = same & (np.abs(ra["post"]).min(axis=1) > 1e-4 * L0) & (np.abs(ra["v2c"]).min(axis=1) > 1e-4 * L0)
-        if not safe.any():
-            continue
+        assert ((ra["post"][ok] < 0) == (rb["post"][ok] < 0)).all()
         for key in ("c2v", "v2c", "post"):
-            x64, x32 = ra[key][safe], rb[key][safe].astype(np.float64)
-            tol = 1e-5 * np.maximum(np.abs(x64), L0)
-            assert (np.abs(x64 - x32) <= tol).all(), key
-        checked += int(safe.sum())
-    assert checked > 1000
+            x64, x32 = ra[key][ok], rb[key][ok].astype(np.float64)
+            assert (np.abs(x64 - x32) <= tol * np.maximum(np.abs(x64), L0)).all(), key
 
 
 def test_decoder_frame_independence(g63_batch):
@@ -314,3 +316,28 @@ def test_decoder_frame_independence(g63_batch):
     full = decoders.decode(g, s[:64], llr, prm, "fp32")
     part = decoders.decode(g, s[20:40], llr, prm, "fp32")
     assert (full.ehat[20:40] == part.ehat).all() and (full.iters[20:40] == part.iters).all()
+
+
+def test_min_sum_exact_ties_with_a_short_prior():
+    """Min-sum with a uniform prior makes every message an integer combination
+    of L0.  When L0 has few significant bits (a float32 value) FP64 sums are
+    exact, posteriors hit exact zeros, and with sgn(0) = +1 the decoder
+    stalls in many frames; rounding residues (a full-precision FP64 prior, or
+    FP32 sums) break those ties instead.  The paper does not address ties;
+    this records the reading's consequence."""
+    hx, hz = codes.gb_matrices(**codes.G63)
+    lz = codes.logical_basis(hz, hx)
+    tg = TannerGraph(hz)
+    p = 0.05
+    ex, _ = channel.sample_paulis(1, 4, 0, 800, 126, p)
+    s = channel.syndrome(hz, ex)
+    prm = DecoderParams(kind="ms", lmax=100)
+    short = np.full(126, channel.prior_llr(p), dtype=np.float32)
+    full = np.full(126, channel.prior_llr(p))
+    fer = {}
+    for name, llr, arith in (("exact", short, "fp64"), ("fp64", full, "fp64"), ("fp32", short, "fp32")):
+        r = decoders.decode(tg, s, llr, prm, arith)
+        fer[name] = judge.judge_logical(lz, ex, r.ehat, r.converged).mean()
+    assert fer["exact"] > 3 * fer["fp64"] and fer["exact"] > 3 * fer["fp32"]
+    lo, hi = stats.wilson(int(round(fer["fp64"] * 800)), 800, z=3.0)
+    assert lo <= fer["fp32"] <= hi
