@@ -41,7 +41,7 @@ def cpu_baseline(p, lmax, params, frames=1 << 13):
     from oracle import channel, codes, decoders, judge
     l, a, b = workloads.code("G63")
     hx, hz = codes.gb_matrices(l, a, b)
-    tg = decoders.TannerGraph(hz)
+    tg = decoders.TannerGraph(hz, codes.gb_var_checks(l, a, b))
     lz = codes.logical_basis(hz, hx)
     llr = np.full(2 * l, channel.prior_llr(p))
     prm = decoders.DecoderParams(kind="sagms", lmax=lmax, **params)
@@ -57,6 +57,14 @@ def cpu_baseline(p, lmax, params, frames=1 << 13):
                       "+ judge, %.1f s" % (frames, frames - 1, dt)}
 
 
+def gb_dense(l, a, b):
+    """Dense (H_Z, H_X) of a GB code, for building it row by row."""
+    eye = np.eye(l, dtype=np.uint8)
+    A = sum(np.roll(eye, e, axis=1) for e in a) % 2
+    B = sum(np.roll(eye, e, axis=1) for e in b) % 2
+    return np.hstack([B.T, A.T]), np.hstack([A, B])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +75,10 @@ def main():
     ap.add_argument("--decoder", default="sagms", choices=["ms", "sms", "sagms", "bp"])
     ap.add_argument("--alpha", type=float, default=0.75)
     ap.add_argument("--lmax", type=int, default=100)
+    ap.add_argument("--graph", default="gb", choices=["gb", "rows"],
+                    help="build the code from its polynomials (posteriors summed in polynomial-term order) or "
+                         "from the rows of H_Z (ascending check order)")
+    ap.add_argument("--frames-per-wave", type=int, default=0, help="decode launch shape (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -82,12 +94,18 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     l, a, b = workloads.code("G63")
-    g = sagms.Graph.gb(l, a, b)
+    if args.graph == "gb":
+        g = sagms.Graph.gb(l, a, b)
+        kernel = "decode_kernel<10,5,1,2,%s>" % ("true" if args.decoder == "bp" else "false")
+    else:
+        g = sagms.Graph.from_dense(*gb_dense(l, a, b))
+        kernel = "decode_kernel<10,5,1,2,%s>" % ("true" if args.decoder == "bp" else "false")
     nf, p = args.frames, args.p
     stream_id = workloads.stream_of(p) if p in workloads.P_GRID else 0
     buf = sagms.frame_buffers(g, nf, device=dev)
     llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
-    cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, **workloads.SAGMS_PARAMS)
+    cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, frames_per_wave=args.frames_per_wave,
+                               **workloads.SAGMS_PARAMS)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -143,7 +161,7 @@ def main():
         "config": {"workload": "GB l=63 [[126,28]] (H_Z: m=63, d_c=10, d_v=5, E=630), code-capacity depolarizing "
                                "p=%g, %d Philox frames/step, %s l_max=%d early exit, flooding, FP32 messages"
                                % (p, nf, args.decoder.upper(), args.lmax),
-                   "code": "G63", "p": p, "frames_per_step": nf, "decoder": args.decoder, "lmax": args.lmax},
+                   "code": "G63", "graph": args.graph, "frames_per_wave": args.frames_per_wave, "p": p, "frames_per_step": nf, "decoder": args.decoder, "lmax": args.lmax},
         "edge_updates_per_s": edge_updates / (total_ms * 1e-3),
         "decode_ms_per_step": mean_dec_ms,
         "decode_frames_per_s": nf / (mean_dec_ms * 1e-3),
@@ -154,7 +172,7 @@ def main():
         "wall_s": wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "decode_kernel<10,5,1,2,false>",
+                     "kernel": kernel,
                      "ops_per_edge_update": OPS_PER_EDGE_UPDATE},
     }
     if not args.no_cpu_baseline:

@@ -76,6 +76,10 @@ typedef struct {
     double alpha_min;
     double alpha_max;
     double eta;
+    int32_t frames_per_wave; /* launch shape: frames decoded one after the other by
+                                one wavefront (0 = library default, else 1..1024);
+                                results do not depend on it */
+    int32_t reserved;        /* must be 0 */
 } sagms_decoder_cfg;
 
 typedef struct sagms_graph_s* sagms_graph;

@@ -45,6 +45,19 @@ def gb_matrices(l: int, a, b) -> tuple[np.ndarray, np.ndarray]:
     return hx, hz
 
 
+def gb_var_checks(l: int, a, b) -> list[list[int]]:
+    """Checks of every variable of H_Z = [B^T | A^T], in polynomial-term order.
+
+    Variable i of the first block meets check (i + b_t) mod l for each term
+    b_t of b(x), variable l + i of the second block meets (i + a_t) mod l;
+    listed in the order of the exponents as given.  This is the order in
+    which a GB graph's FP32 posterior sums are taken.
+    """
+    first = [[(i + t) % l for t in b] for i in range(l)]
+    second = [[(i + t) % l for t in a] for i in range(l)]
+    return first + second
+
+
 def dimension(hx, hz) -> int:
     """k = n - rank H_X - rank H_Z of a CSS code."""
     n = np.asarray(hx).shape[1]

@@ -48,6 +48,9 @@ Arithmetic modes
           BP in this mode evaluates the CN in double from FP32 inputs and
           rounds the output to FP32.
   Signed zeros of L0 are read as +0 in both modes.
+  The order of a variable's checks in the FP32 posterior sum is part of the
+  graph: ascending check index by default, or an explicit order (for a GB
+  code, the order of the terms of its polynomials; codes.gb_var_checks).
 """
 from __future__ import annotations
 
@@ -91,11 +94,12 @@ class TannerGraph:
 
     Edges are numbered check-major (check i's edges are consecutive, in
     ascending variable index).  cn_edge[i] lists check i's edges, vn_edge[j]
-    variable j's edges in ascending check index; both are padded with the
-    sentinel index E (one extra message slot).
+    variable j's edges in ascending check index, or in the order given by
+    var_checks[j] (a permutation of j's checks); both tables are padded with
+    the sentinel index E (one extra message slot).
     """
 
-    def __init__(self, h):
+    def __init__(self, h, var_checks=None):
         h = (np.asarray(h, dtype=np.uint8) & 1)
         self.h = h
         self.m, self.n = h.shape
@@ -119,6 +123,13 @@ class TannerGraph:
             fill_c[i] += 1
             self.vn_edge[j, fill_v[j]] = e  # ascending check index
             fill_v[j] += 1
+        if var_checks is not None:
+            edge_of = {(int(self.e_check[e]), int(self.e_var[e])): e for e in range(self.E)}
+            for j in range(self.n):
+                order = [int(c) for c in var_checks[j]]
+                if sorted(order) != sorted(int(self.e_check[e]) for e in self.vn_edge[j] if e < self.E):
+                    raise ValueError("var_checks[%d] is not a permutation of the variable's checks" % j)
+                self.vn_edge[j, :len(order)] = [edge_of[(c, j)] for c in order]
 
 
 def check_gains(p: DecoderParams, sres: np.ndarray, m: int) -> np.ndarray:

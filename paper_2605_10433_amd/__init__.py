@@ -37,7 +37,8 @@ class SagmsError(RuntimeError):
 class DecoderConfig(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("schedule", ctypes.c_int32), ("lmax", ctypes.c_int32),
                 ("msg_precision", ctypes.c_int32), ("alpha", ctypes.c_double), ("alpha_min", ctypes.c_double),
-                ("alpha_max", ctypes.c_double), ("eta", ctypes.c_double)]
+                ("alpha_max", ctypes.c_double), ("eta", ctypes.c_double), ("frames_per_wave", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -93,10 +94,12 @@ def prior_llr(p: float) -> float:
     return float(lib().sagms_prior_llr(float(p)))
 
 
-def decoder_config(kind="sagms", lmax=100, alpha=0.75, alpha_min=0.30, alpha_max=0.50, eta=1.10) -> DecoderConfig:
+def decoder_config(kind="sagms", lmax=100, alpha=0.75, alpha_min=0.30, alpha_max=0.50, eta=1.10,
+                   frames_per_wave=0) -> DecoderConfig:
     if kind not in KINDS:
         raise ValueError("unknown decoder kind %r" % kind)
-    return DecoderConfig(KINDS[kind], 0, int(lmax), 0, float(alpha), float(alpha_min), float(alpha_max), float(eta))
+    return DecoderConfig(KINDS[kind], 0, int(lmax), 0, float(alpha), float(alpha_min), float(alpha_max), float(eta),
+                         int(frames_per_wave), 0)
 
 
 class Graph:

@@ -7,7 +7,7 @@ using namespace sagms;
 
 namespace {
 
-constexpr int kDecodeFramesPerWave = 4;
+constexpr int kDecodeFramesPerWave = 8;
 constexpr int kSampleFramesPerWave = 4;
 
 int check_cfg(const sagms_decoder_cfg* c) {
@@ -16,6 +16,9 @@ int check_cfg(const sagms_decoder_cfg* c) {
     if (c->schedule != SAGMS_FLOODING) return fail(SAGMS_EUNSUPPORTED, "only the flooding schedule is implemented");
     if (c->msg_precision != SAGMS_MSG_FP32) return fail(SAGMS_EUNSUPPORTED, "message precision %d not available", c->msg_precision);
     if (c->lmax < 1) return fail(SAGMS_EINVAL, "lmax must be >= 1 (got %d)", c->lmax);
+    if (c->frames_per_wave < 0 || c->frames_per_wave > 1024)
+        return fail(SAGMS_EINVAL, "frames_per_wave must lie in [0, 1024]");
+    if (c->reserved != 0) return fail(SAGMS_EINVAL, "reserved field must be 0");
     if (c->kind == SAGMS_SMS && !(c->alpha > 0.0 && c->alpha <= 1.0))
         return fail(SAGMS_EINVAL, "SMS alpha must lie in (0, 1]");
     if (c->kind == SAGMS_SAGMS) {
@@ -46,6 +49,7 @@ int sagms_gen_errors(sagms_graph gh, uint64_t seed, uint32_t stream_id, uint64_t
     if (rc) return rc;
     SampleArgs a{};
     a.cols = t->cols;
+    a.rows = t->rows;
     a.ex = ex;
     a.ez = ez;
     a.synd = synd;
@@ -114,7 +118,7 @@ int sagms_decode_soft(sagms_graph gh, const uint64_t* synd, const float* llr0, c
     a.wm = g->wm;
     a.wn = g->wn;
     a.lmax = cfg->lmax;
-    a.frames_per_wave = kDecodeFramesPerWave;
+    a.frames_per_wave = cfg->frames_per_wave > 0 ? cfg->frames_per_wave : kDecodeFramesPerWave;
     a.L = g->layout;
     return launch_decode(g->shape, cfg->kind == SAGMS_BP, a, 0, st);
 }

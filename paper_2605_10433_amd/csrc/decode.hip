@@ -18,8 +18,9 @@
 //            taken from a table indexed by w and by the check's residual
 //            bit (eq. (alphaeff); 1 for MS, alpha for SMS).  BP replaces
 //            this by eq. (bp4_cn) in tanh form, evaluated in FP64.
-//     VN     every variable sums L0 and its incoming c2v messages in
-//            ascending check order and stores the posterior (eq. (bp4_vn)).
+//     VN     every variable sums L0 and its incoming c2v messages in the
+//            graph's order (ascending check index, or polynomial-term order
+//            for a GB code) and stores the posterior (eq. (bp4_vn)).
 //   The hard decision is e_hat_j = [posterior_j < 0].
 // Posteriors and v2c messages are never -0.0 (L0 is read as L0 + 0.0f and
 // every later value is a sum or a difference of finite floats starting from
@@ -64,17 +65,86 @@ __device__ __forceinline__ void bp_magnitudes(const float (&v)[DC], float (&out)
     }
 }
 
+// Compile-time LDS layout of one wave (32-bit words); must equal make_layout().
+template <int DC, int CPL, int VPL>
+struct Lay {
+    static constexpr int CW = 64 * CPL;
+    static constexpr int ZERO = DC * CW;
+    static constexpr int POST0 = ZERO + 1;
+    static constexpr int PADPOST = POST0 + 64 * VPL;
+    static constexpr int GAIN0 = (PADPOST + 2) & ~1;
+    static constexpr int WORDS = GAIN0 + 2 * (CW + 1);
+};
+
+__device__ __forceinline__ uint32_t bits(float x) { return __float_as_uint(x); }
+
+// gfx950 3-input bit operations (truth table indexed by a*4 + b*2 + c):
+// a ^ b ^ c (0x96) and a ^ (b & c) (0x78).  The compiler re-associates XOR
+// chains into 2-input steps unless asked for the 3-input form.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x78);
+}
+
+// Sign bit of init XOR the signs of x[0..N-1], two inputs per step.
+template <int N>
+__device__ __forceinline__ uint32_t xor_signs(const float (&x)[N], uint32_t init) {
+    uint32_t acc = init;
+#pragma unroll
+    for (int p = 0; p + 1 < N; p += 2) acc = xor3(acc, bits(x[p]), bits(x[p + 1]));
+    if constexpr (N % 2) acc ^= bits(x[N - 1]);
+    return acc & kSign;
+}
+
+// Check-node update of one check (eq. (ms_cn) scaled per eq. (alphaeff) /
+// (sagms_cn), or eq. (bp4_cn) for BP): v = incoming v2c messages, sb = the
+// original syndrome bit, res = the residual bit (both at the sign position),
+// gs / gu = the gains of a satisfied / unsatisfied check.
+template <int DC, bool BP>
+__device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, uint32_t res, float gs, float gu,
+                                          float (&c2v)[DC]) {
+    const uint32_t par = xor_signs<DC>(v, sb);
+    if constexpr (BP) {
+        float mag[DC];
+        bp_magnitudes<DC>(v, mag);
+#pragma unroll
+        for (int p = 0; p < DC; ++p) c2v[p] = __uint_as_float(bits(mag[p]) | ((bits(v[p]) ^ par) & kSign));
+    } else {
+        const float alpha = res ? gu : gs;
+        float m1 = __builtin_inff(), m2 = __builtin_inff();
+#pragma unroll
+        for (int p = 0; p < DC; ++p) {
+            float x = fabsf(v[p]);
+            m2 = __builtin_amdgcn_fmed3f(m1, x, m2);
+            m1 = fminf(m1, x);
+        }
+        // two products per check, both magnitudes pre-signed with the check
+        // parity; per edge: compare, select, and one 3-input bit operation
+        // applying the edge's own sign.  The empty asm keeps the compiler
+        // from folding the select back into one product per edge.
+        uint32_t S1 = bits(alpha * m1) | par, S2 = bits(alpha * m2) | par;
+        asm("" : "+v"(S1), "+v"(S2));
+#pragma unroll
+        for (int p = 0; p < DC; ++p) {
+            const uint32_t sel = fabsf(v[p]) == m1 ? S2 : S1;
+            c2v[p] = __uint_as_float(xor_and(sel, bits(v[p]), kSign));
+        }
+    }
+}
+
 template <int DC, int DV, int CPL, int VPL, bool BP>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs a) {
+    using LY = Lay<DC, CPL, VPL>;
     extern __shared__ float lds_all[];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
-    float* lds = lds_all + wib * a.L.words;
+    float* lds = lds_all + wib * LY::WORDS;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
     const int64_t f_begin = wave * a.frames_per_wave;
     if (f_begin >= a.nframes) return;
     const int64_t f_end = min(f_begin + (int64_t)a.frames_per_wave, a.nframes);
-    const int cw = a.L.cw;
 
     // graph tables and priors: loaded once per wave
     uint32_t caddr[CPL][DC];
@@ -93,27 +163,30 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
         int j = k * 64 + lane;
         L0[k] = j < a.n ? a.llr0[j] + 0.0f : __builtin_inff();
     }
-    bool cvalid[CPL];
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) cvalid[k] = k * 64 + lane < a.m;
-    for (int t = lane; t < 2 * (cw + 1); t += 64) lds[a.L.gain0 + t] = a.gains[t];
+    // gain table: in registers (lane w holds entry w) when m <= 64, else in LDS
+    const float gsl = a.gains[2 * lane], gul = a.gains[2 * lane + 1];
+    const float gs64 = a.gains[128], gu64 = a.gains[129];
+    if constexpr (CPL > 1)
+        for (int t = lane; t < 2 * (LY::CW + 1); t += 64) lds[LY::GAIN0 + t] = a.gains[t];
     if (lane == 0) {
-        lds[a.L.zero] = 0.0f;
-        lds[a.L.padpost] = __builtin_inff();
+        lds[LY::ZERO] = 0.0f;
+        lds[LY::PADPOST] = __builtin_inff();
     }
 
     for (int64_t f = f_begin; f < f_end; ++f) {
-        uint32_t sb[CPL];  // original syndrome bit of each owned check, at the sign position
+        // original syndrome bit of each owned check, at the sign position
+        // (checks beyond m read as 0; their rows hold only the +inf padding)
+        uint32_t sb[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             uint64_t word = k < a.wm ? a.synd[f * a.wm + k] : 0ull;
-            sb[k] = cvalid[k] ? (uint32_t)((word >> lane) & 1ull) << 31 : 0u;
+            sb[k] = (k * 64 + lane < a.m) ? (uint32_t)((word >> lane) & 1ull) << 31 : 0u;
         }
         float post[VPL];
 #pragma unroll
         for (int k = 0; k < VPL; ++k) {
             post[k] = L0[k];
-            lds[a.L.post0 + k * 64 + lane] = L0[k];
+            lds[LY::POST0 + k * 64 + lane] = L0[k];
         }
         float c2v[CPL][DC];
 #pragma unroll
@@ -127,19 +200,18 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
         while (true) {
             // top of the round: v2c, hard-decision parity, residual syndrome
             float v[CPL][DC];
-            bool unsat[CPL];
+            uint32_t res[CPL];  // residual syndrome bit at the sign position
             int w = 0;
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
-                uint32_t hd = 0;
+                float pj[DC];
 #pragma unroll
                 for (int p = 0; p < DC; ++p) {
-                    float pj = lds[caddr[k][p]];
-                    v[k][p] = pj - c2v[k][p];
-                    hd ^= __float_as_uint(pj);
+                    pj[p] = lds[caddr[k][p]];
+                    v[k][p] = pj[p] - c2v[k][p];
                 }
-                unsat[k] = cvalid[k] && ((hd ^ sb[k]) & kSign);
-                w += __builtin_popcountll(ballot(unsat[k]));
+                res[k] = xor_signs<DC>(pj, sb[k]);
+                w += __builtin_popcountll(ballot(res[k] != 0));
             }
             if (w == 0) {
                 conv = true;
@@ -147,50 +219,31 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
             }
             if (it == a.lmax) break;
             ++it;
-            // CN update
-            const float2 gg = *reinterpret_cast<const float2*>(&lds[a.L.gain0 + 2 * w]);
+            // CN update; gains of the residual weight w (eq. (alphaeff))
+            float gs, gu;
+            if constexpr (CPL == 1) {
+                gs = w < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gsl), w)) : gs64;
+                gu = w < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gul), w)) : gu64;
+            } else {
+                const float2 gg = *reinterpret_cast<const float2*>(&lds[LY::GAIN0 + 2 * w]);
+                gs = gg.x;
+                gu = gg.y;
+            }
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
-                uint32_t par = sb[k];
+                cn_update<DC, BP>(v[k], sb[k], res[k], gs, gu, c2v[k]);
 #pragma unroll
-                for (int p = 0; p < DC; ++p) par ^= __float_as_uint(v[k][p]);
-                par &= kSign;
-                if constexpr (BP) {
-                    float mag[DC];
-                    bp_magnitudes<DC>(v[k], mag);
-#pragma unroll
-                    for (int p = 0; p < DC; ++p)
-                        c2v[k][p] = __uint_as_float(__float_as_uint(mag[p]) |
-                                                    ((__float_as_uint(v[k][p]) ^ par) & kSign));
-                } else {
-                    const float alpha = unsat[k] ? gg.y : gg.x;
-                    float m1 = __builtin_inff(), m2 = __builtin_inff();
-#pragma unroll
-                    for (int p = 0; p < DC; ++p) {
-                        float x = fabsf(v[k][p]);
-                        m2 = __builtin_amdgcn_fmed3f(m1, x, m2);
-                        m1 = fminf(m1, x);
-                    }
-                    const float s1 = alpha * m1, s2 = alpha * m2;
-#pragma unroll
-                    for (int p = 0; p < DC; ++p) {
-                        float mag = fabsf(v[k][p]) == m1 ? s2 : s1;
-                        c2v[k][p] = __uint_as_float(__float_as_uint(mag) |
-                                                    ((__float_as_uint(v[k][p]) ^ par) & kSign));
-                    }
-                }
-#pragma unroll
-                for (int p = 0; p < DC; ++p) lds[p * cw + k * 64 + lane] = c2v[k][p];
+                for (int p = 0; p < DC; ++p) lds[p * LY::CW + k * 64 + lane] = c2v[k][p];
             }
             wave_lds_sync();
-            // VN update: posterior in ascending check order
+            // VN update: posterior in the graph's summation order
 #pragma unroll
             for (int k = 0; k < VPL; ++k) {
                 float s = L0[k];
 #pragma unroll
                 for (int r = 0; r < DV; ++r) s = s + lds[vaddr[k][r]];
                 post[k] = s;
-                lds[a.L.post0 + k * 64 + lane] = s;
+                lds[LY::POST0 + k * 64 + lane] = s;
             }
             wave_lds_sync();
         }
@@ -226,6 +279,10 @@ static int waves_per_block(const DecodeLayout& L) {
 
 template <int DC, int DV, int CPL, int VPL>
 static int launch_shape(bool bp, const DecodeArgs& a, hipStream_t st) {
+    using LY = Lay<DC, CPL, VPL>;
+    if (a.L.cw != LY::CW || a.L.zero != LY::ZERO || a.L.post0 != LY::POST0 || a.L.padpost != LY::PADPOST ||
+        a.L.gain0 != LY::GAIN0 || a.L.words != LY::WORDS)
+        return fail(SAGMS_EUNSUPPORTED, "decode layout mismatch (internal)");
     if ((size_t)a.L.words * sizeof(float) > 65536) return fail(SAGMS_EUNSUPPORTED, "graph too large for one wave's LDS");
     const int wpb = waves_per_block(a.L);
     int64_t waves = (a.nframes + a.frames_per_wave - 1) / a.frames_per_wave;

@@ -109,21 +109,35 @@ static void build_lane_tables(Graph* g) {
     const DecodeLayout& L = g->layout;
     g->cn_addr_host.assign((size_t)s.cpl * s.dc * 64, (uint32_t)L.padpost);
     g->vn_addr_host.assign((size_t)s.vpl * s.dv * 64, (uint32_t)L.zero);
-    // variable -> (check, position) in ascending check order
-    std::vector<std::vector<std::pair<int, int>>> adj(g->n);
     for (int c = 0; c < g->m; ++c)
         for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p) {
             int j = g->cols[g->row_ptr[c] + p];
-            adj[j].push_back({c, p});
             g->cn_addr_host[((size_t)(c / 64) * s.dc + p) * 64 + (c % 64)] = (uint32_t)(L.post0 + j);
         }
-    for (int j = 0; j < g->n; ++j) {
-        std::sort(adj[j].begin(), adj[j].end());
-        for (size_t r = 0; r < adj[j].size(); ++r) {
-            int c = adj[j][r].first, p = adj[j][r].second;
+    for (int j = 0; j < g->n; ++j)
+        for (size_t r = 0; r < g->var_edges[j].size(); ++r) {
+            int c = g->var_edges[j][r].first, p = g->var_edges[j][r].second;
             g->vn_addr_host[((size_t)(j / 64) * s.dv + r) * 64 + (j % 64)] = (uint32_t)(p * L.cw + c);
         }
+}
+
+// Every variable's (check, position) pairs in posterior-sum order: ascending
+// check index, or for a GB code the order of the polynomial terms (variable
+// i of the first block meets check (i + b_t) mod l at position t, variable
+// l + i of the second block check (i + a_t) mod l at position wb + t).
+static void build_var_edges(Graph* g) {
+    g->var_edges.assign(g->n, {});
+    if (g->is_gb) {
+        const int l = g->gb_l, wb = (int)g->gb_b.size();
+        for (int i = 0; i < l; ++i) {
+            for (int t = 0; t < wb; ++t) g->var_edges[i].push_back({(i + g->gb_b[t]) % l, t});
+            for (int t = 0; t < (int)g->gb_a.size(); ++t) g->var_edges[l + i].push_back({(i + g->gb_a[t]) % l, wb + t});
+        }
+        return;
     }
+    for (int c = 0; c < g->m; ++c)
+        for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p) g->var_edges[g->cols[g->row_ptr[c] + p]].push_back({c, p});
+    for (auto& v : g->var_edges) std::sort(v.begin(), v.end());
 }
 
 // ---- graph construction ------------------------------------------------
@@ -179,6 +193,7 @@ static int finish_graph(Graph* g, const std::vector<int>& row_ptr_o, const std::
         }
         g->k = (int)(g->logicals.size() / g->wn);
     }
+    build_var_edges(g);
     g->shape_ok = pick_shape(g->m, g->n, g->dc_max, g->dv_max, &g->shape);
     if (g->shape_ok) {
         g->layout = make_layout(g->shape);
@@ -207,11 +222,18 @@ static int check_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci,
 }
 
 static int build(int32_t m, int32_t n, const std::vector<int>& rp, const std::vector<int>& ci, int32_t m_other,
-                 const std::vector<int>& rpo, const std::vector<int>& cio, sagms_graph* out) {
+                 const std::vector<int>& rpo, const std::vector<int>& cio, sagms_graph* out,
+                 const std::vector<int>* gb_a = nullptr, const std::vector<int>* gb_b = nullptr) {
     Graph* g = new (std::nothrow) Graph();
     if (!g) return fail(SAGMS_ENOMEM, "graph allocation failed");
     g->m = m;
     g->n = n;
+    if (gb_a && gb_b) {
+        g->is_gb = true;
+        g->gb_l = m;
+        g->gb_a = *gb_a;
+        g->gb_b = *gb_b;
+    }
     g->row_ptr = rp;
     g->cols = ci;
     int rc = finish_graph(g, rpo, cio, m_other);
@@ -238,6 +260,9 @@ int device_tables(Graph* g, DeviceTables** out, hipStream_t stream) {
                 cols[(size_t)c * std::max(g->dc_max, 1) + p] = g->cols[g->row_ptr[c] + p];
         SAGMS_HIP(hipMalloc(&t->cols, std::max<size_t>(ncols, 1) * sizeof(int32_t)));
         SAGMS_HIP(hipMemcpy(t->cols, cols.data(), ncols * sizeof(int32_t), hipMemcpyHostToDevice));
+        SAGMS_HIP(hipMalloc(&t->rows, g->rows_bits.size() * sizeof(uint64_t)));
+        SAGMS_HIP(hipMemcpy(t->rows, g->rows_bits.data(), g->rows_bits.size() * sizeof(uint64_t),
+                            hipMemcpyHostToDevice));
         if (g->shape_ok) {
             SAGMS_HIP(hipMalloc(&t->cn_addr, g->cn_addr_host.size() * sizeof(uint32_t)));
             SAGMS_HIP(hipMemcpy(t->cn_addr, g->cn_addr_host.data(), g->cn_addr_host.size() * sizeof(uint32_t),
@@ -357,7 +382,8 @@ int sagms_build_gb(int32_t l, const int32_t* a, int32_t wa, const int32_t* b, in
         for (int t = 0; t < wb; ++t) cio.push_back(l + (c + b[t]) % l);
     }
     rpo[l] = (int)cio.size();
-    return build(l, 2 * l, rp, ci, l, rpo, cio, out);
+    std::vector<int> va(a, a + wa), vb(b, b + wb);
+    return build(l, 2 * l, rp, ci, l, rpo, cio, out, &va, &vb);
 }
 
 int sagms_graph_info(sagms_graph gh, sagms_graph_info_t* info) {
@@ -399,6 +425,7 @@ int sagms_destroy_graph(sagms_graph gh) {
         if (!t.ready) continue;
         if (have_dev) (void)hipSetDevice(d);
         (void)hipFree(t.cols);
+        (void)hipFree(t.rows);
         (void)hipFree(t.cn_addr);
         (void)hipFree(t.vn_addr);
         (void)hipFree(t.logicals);

@@ -58,6 +58,7 @@ struct DeviceTables {
     uint32_t* cn_addr = nullptr;   // [cpl * dc][64] LDS word index of the posterior read at (check, pos)
     uint32_t* vn_addr = nullptr;   // [vpl * dv][64] LDS word index of the c2v slot read at (var, rank)
     int32_t* cols = nullptr;       // [m][dc_max] column of (check, pos), -1 padded (sampler)
+    uint64_t* rows = nullptr;      // [m][words_n] packed rows of H (sampler)
     uint64_t* logicals = nullptr;  // [k][words_n]
     std::map<GainKey, float*> gains;
     std::map<GainKey, std::vector<float>> gains_host;  // kept alive for async uploads
@@ -71,6 +72,12 @@ struct Graph {
     std::vector<uint64_t> rows_bits;   // [m][wn]
     std::vector<uint64_t> logicals;    // [k][wn]
     bool have_other = false;
+    // GB codes: circulant size and exponents (term order of the polynomials)
+    bool is_gb = false;
+    int gb_l = 0;
+    std::vector<int> gb_a, gb_b;
+    // every variable's (check, position) pairs in the order of its posterior sum
+    std::vector<std::vector<std::pair<int, int>>> var_edges;
     bool shape_ok = false;
     DecodeShape shape{};
     DecodeLayout layout{};
@@ -108,8 +115,10 @@ struct DecodeArgs {
 };
 int launch_decode(const DecodeShape& s, bool bp, const DecodeArgs& a, int waves_per_block, hipStream_t st);
 
+
 struct SampleArgs {
     const int32_t* cols;
+    const uint64_t* rows;
     uint64_t* ex;
     uint64_t* ez;
     uint64_t* synd;
@@ -118,7 +127,7 @@ struct SampleArgs {
     int64_t nframes;
     uint32_t stream_id;
     uint32_t tx, ty, tz;
-    int m, n, dc, wn, wm, frames_per_wave;
+    int m, n, dc, wn, wm, frames_per_wave, lanes_per_frame;
 };
 int launch_sample(const SampleArgs& a, hipStream_t st);
 

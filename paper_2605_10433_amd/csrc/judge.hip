@@ -1,47 +1,108 @@
 // Logical-failure judge: frame f fails iff it did not converge or the
 // residual r = e_x xor e_hat has odd overlap with a row of the logical basis
 // (a basis of ker(H_other) modulo rowspace(H)), i.e. r is not a stabilizer.
-// One thread per frame; the basis rows are wave-uniform loads.  Failures
-// and iteration counts are reduced per wave and added with one atomic each.
+// A bounded grid of blocks strides over the frames, one frame per thread at
+// a time: the residual words stay in registers, the basis is staged in LDS
+// (read at wave-uniform addresses) and every row's parity is evaluated
+// without an early exit.  Failure and round counts are reduced per thread,
+// then per block, and added with one atomic per block and counter (atomics
+// on one address serialise, so their number is kept to the grid size).
 #include "internal.h"
 
 namespace sagms {
 
 constexpr int kJudgeBlock = 256;
+constexpr int kJudgeMaxBlocks = 1024;
+constexpr size_t kJudgeLdsMax = 32768;
 
-__global__ void __launch_bounds__(kJudgeBlock) judge_kernel(JudgeArgs a) {
-    const int64_t f = (int64_t)blockIdx.x * kJudgeBlock + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    bool failed = false;
-    int32_t it = 0;
-    if (f < a.nframes) {
-        it = a.iters[f];
-        failed = a.conv[f] == 0;
-        if (!failed) {
-            const uint64_t* x = a.ex + f * a.wn;
-            const uint64_t* e = a.ehat + f * a.wn;
-            for (int t = 0; t < a.k && !failed; ++t) {
-                uint32_t par = 0;
-                for (int w = 0; w < a.wn; ++w) par ^= __builtin_popcountll((x[w] ^ e[w]) & a.logicals[(size_t)t * a.wn + w]);
-                failed = par & 1u;
-            }
-        }
-        if (a.fail) a.fail[f] = failed ? 1 : 0;
+__device__ __forceinline__ bool judge_frame_any(const JudgeArgs& a, int64_t f) {
+    const uint64_t* x = a.ex + f * a.wn;
+    const uint64_t* e = a.ehat + f * a.wn;
+    uint32_t odd = 0;
+    for (int t = 0; t < a.k; ++t) {
+        uint32_t cnt = 0;
+        for (int w = 0; w < a.wn; ++w) cnt += __builtin_popcountll((x[w] ^ e[w]) & a.logicals[(size_t)t * a.wn + w]);
+        odd |= cnt;
     }
-    // wave reductions, one atomic per wave and counter
-    uint64_t nfail = __builtin_popcountll(__builtin_amdgcn_ballot_w64(failed));
-    uint64_t isum = (uint64_t)it;
-    for (int off = 32; off > 0; off >>= 1) isum += __shfl_xor(isum, off, 64);
-    if (lane == 0 && (int64_t)blockIdx.x * kJudgeBlock + threadIdx.x < a.nframes) {
-        if (nfail) atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)nfail);
-        if (isum) atomicAdd((unsigned long long*)&a.counters[1], (unsigned long long)isum);
+    return a.conv[f] == 0 || (odd & 1u);
+}
+
+template <int WN>
+__device__ __forceinline__ bool judge_frame(const JudgeArgs& a, const uint64_t* lg, int64_t f) {
+    uint64_t r[WN];
+#pragma unroll
+    for (int w = 0; w < WN; ++w) r[w] = w < a.wn ? a.ex[f * a.wn + w] ^ a.ehat[f * a.wn + w] : 0ull;
+    uint32_t odd = 0;
+    for (int t = 0; t < a.k; ++t) {
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int w = 0; w < WN; ++w)
+            if (w < a.wn) cnt += __builtin_popcountll(r[w] & lg[t * a.wn + w]);
+        odd |= cnt;
+    }
+    return a.conv[f] == 0 || (odd & 1u);
+}
+
+// WN = 0: basis and residual read from global memory (any size).
+template <int WN>
+__global__ void __launch_bounds__(kJudgeBlock) judge_kernel(JudgeArgs a) {
+    extern __shared__ uint64_t lg[];
+    __shared__ unsigned long long part[2][kJudgeBlock / 64];
+    if constexpr (WN > 0) {
+        for (int t = threadIdx.x; t < a.k * a.wn; t += kJudgeBlock) lg[t] = a.logicals[t];
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * kJudgeBlock;
+    uint64_t nfail = 0, isum = 0;
+    for (int64_t f = (int64_t)blockIdx.x * kJudgeBlock + threadIdx.x; f < a.nframes; f += stride) {
+        bool failed;
+        if constexpr (WN > 0)
+            failed = judge_frame<WN>(a, lg, f);
+        else
+            failed = judge_frame_any(a, f);
+        if (a.fail) a.fail[f] = failed ? 1 : 0;
+        nfail += failed ? 1 : 0;
+        isum += (uint64_t)a.iters[f];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nfail += __shfl_xor(nfail, off, 64);
+        isum += __shfl_xor(isum, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        part[0][wid] = nfail;
+        part[1][wid] = isum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s0 = 0, s1 = 0;
+        for (int t = 0; t < kJudgeBlock / 64; ++t) {
+            s0 += part[0][t];
+            s1 += part[1][t];
+        }
+        if (s0) atomicAdd((unsigned long long*)&a.counters[0], s0);
+        if (s1) atomicAdd((unsigned long long*)&a.counters[1], s1);
     }
 }
 
 int launch_judge(const JudgeArgs& a, hipStream_t st) {
     int64_t blocks = (a.nframes + kJudgeBlock - 1) / kJudgeBlock;
-    if (blocks > 0x7fffffff) return fail(SAGMS_EINVAL, "too many frames for one launch");
-    hipLaunchKernelGGL(judge_kernel, dim3((unsigned)blocks), dim3(kJudgeBlock), 0, st, a);
+    if (blocks > kJudgeMaxBlocks) blocks = kJudgeMaxBlocks;
+    const size_t lds = (size_t)a.k * a.wn * sizeof(uint64_t);
+    const dim3 grid((unsigned)blocks), block(kJudgeBlock);
+#define WNS(WN)                                                                      \
+    if (lds <= kJudgeLdsMax && a.wn <= WN) {                                         \
+        hipLaunchKernelGGL((judge_kernel<WN>), grid, block, lds, st, a);             \
+        SAGMS_HIP(hipGetLastError());                                                \
+        return SAGMS_OK;                                                             \
+    }
+    WNS(1)
+    WNS(2)
+    WNS(4)
+    WNS(8)
+    WNS(16)
+#undef WNS
+    hipLaunchKernelGGL((judge_kernel<0>), grid, block, 0, st, a);
     SAGMS_HIP(hipGetLastError());
     return SAGMS_OK;
 }

@@ -7,9 +7,14 @@
 // integer thresholds T_X <= T_Y <= T_Z select X, Y, Z, so e_x = [u < T_Y] and
 // e_z = [T_X <= u < T_Z].  The syndrome is s = H e_x over GF(2).
 //
-// One wavefront handles one frame at a time: lanes evaluate Philox blocks,
-// write the X / Z bit of every qubit to LDS as bytes, then ballots over
-// 64 consecutive qubits (or checks) produce the packed words.
+// A wavefront samples several frames per pass when a frame needs fewer than
+// 64 Philox blocks (lanes_per_frame lanes each), so every lane evaluates one
+// block.  Each lane stores its four X (and Z) bits as one 32-bit word of
+// bytes in LDS; ballots over 64 consecutive qubits then give the packed
+// words, which are wave-uniform.  Syndromes: for small codes every lane
+// holds the packed rows of its checks in registers and takes the parity of
+// (row AND e_x) with popcounts; larger codes gather the error bytes of each
+// check's columns from LDS.
 #include "internal.h"
 
 namespace sagms {
@@ -39,73 +44,182 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-__global__ void __launch_bounds__(64 * kSampleWavesPerBlock) sample_kernel(SampleArgs a) {
+// Philox pass: frames [fb, fb + 64 / lpf) (those below f_end), one block per
+// lane and per stride; X / Z bits of qubit q land in byte q of the frame's
+// LDS planes (padding qubits get 0).
+__device__ __forceinline__ void philox_pass(const SampleArgs& a, unsigned char* xb, unsigned char* zb, int nq,
+                                            int64_t fb, int64_t f_end, int lane) {
+    const int fs = lane / a.lanes_per_frame;
+    const int64_t f = fb + fs;
+    if (f >= f_end) return;
+    const uint64_t frame = a.frame0 + (uint64_t)f;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const int calls = (a.n + 3) / 4;
+    for (int t = lane % a.lanes_per_frame; t < calls; t += a.lanes_per_frame) {
+        uint4 u = philox4x32_10(make_uint4((uint32_t)t, (uint32_t)frame, (uint32_t)(frame >> 32), a.stream_id), k0, k1);
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+        uint32_t xw = 0, zw = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const bool in = 4 * t + b < a.n;
+            xw |= (uint32_t)(in && w[b] < a.ty) << (8 * b);
+            zw |= (uint32_t)(in && w[b] >= a.tx && w[b] < a.tz) << (8 * b);
+        }
+        *reinterpret_cast<uint32_t*>(xb + (size_t)fs * nq + 4 * t) = xw;
+        *reinterpret_cast<uint32_t*>(zb + (size_t)fs * nq + 4 * t) = zw;
+    }
+}
+
+// Bytes of qubits at and beyond 4 * blocks are never written by a pass:
+// zero them once per wave in every frame slot of both planes.
+__device__ __forceinline__ void zero_tail(const SampleArgs& a, unsigned char* xb, int nq, int lane) {
+    const int fpp = 64 / a.lanes_per_frame;
+    const int q0 = 4 * ((a.n + 3) / 4);
+    for (int fs = 0; fs < 2 * fpp; ++fs)
+        for (int q = q0 + lane; q < nq; q += 64) xb[(size_t)fs * nq + q] = 0;
+}
+
+// Small codes: n <= 64 * WN, m <= 64 * CPLS, rows of H in registers.
+template <int WN, int CPLS>
+__global__ void __launch_bounds__(64 * kSampleWavesPerBlock) sample_kernel_rows(SampleArgs a) {
     extern __shared__ unsigned char slds[];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
-    const int nq = (a.n + 63) & ~63;            // qubit bytes per plane, padded to 64
-    unsigned char* xb = slds + (size_t)wib * 2 * nq;
-    unsigned char* zb = xb + nq;
+    const int fpp = 64 / a.lanes_per_frame;
+    constexpr int nq = 64 * WN;
+    unsigned char* xb = slds + (size_t)wib * 2 * fpp * nq;
+    unsigned char* zb = xb + (size_t)fpp * nq;
     const int64_t wave = (int64_t)blockIdx.x * kSampleWavesPerBlock + wib;
     const int64_t f_begin = wave * a.frames_per_wave;
     if (f_begin >= a.nframes) return;
     const int64_t f_end = min(f_begin + (int64_t)a.frames_per_wave, a.nframes);
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const int calls = (a.n + 3) / 4;
-    for (int q = a.n + lane; q < nq; q += 64) {  // padding qubits stay zero
-        xb[q] = 0;
-        zb[q] = 0;
+
+    zero_tail(a, xb, nq, lane);
+    uint64_t row[CPLS][WN];
+#pragma unroll
+    for (int k = 0; k < CPLS; ++k) {
+        const int c = 64 * k + lane;
+#pragma unroll
+        for (int w = 0; w < WN; ++w) row[k][w] = (c < a.m && w < a.wn) ? a.rows[(size_t)c * a.wn + w] : 0ull;
     }
 
-    for (int64_t f = f_begin; f < f_end; ++f) {
-        const uint64_t frame = a.frame0 + (uint64_t)f;
-        for (int t = lane; t < calls; t += 64) {
-            uint4 u = philox4x32_10(make_uint4((uint32_t)t, (uint32_t)frame, (uint32_t)(frame >> 32), a.stream_id),
-                                    k0, k1);
-            const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                int q = 4 * t + b;
-                if (q < a.n) {
-                    xb[q] = w[b] < a.ty;
-                    zb[q] = (w[b] >= a.tx) & (w[b] < a.tz);
-                }
-            }
-        }
+    for (int64_t fb = f_begin; fb < f_end; fb += fpp) {
+        philox_pass(a, xb, zb, nq, fb, f_end, lane);
         wave_lds_sync_s();
-        for (int wd = 0; wd < a.wn; ++wd) {
-            const int q = 64 * wd + lane;
-            uint64_t wx = __builtin_amdgcn_ballot_w64(xb[q] != 0);
-            uint64_t wz = __builtin_amdgcn_ballot_w64(zb[q] != 0);
-            if (lane == 0) {
-                a.ex[f * a.wn + wd] = wx;
-                if (a.ez) a.ez[f * a.wn + wd] = wz;
-            }
-        }
-        for (int wd = 0; wd < a.wm; ++wd) {
-            const int c = 64 * wd + lane;
-            uint32_t par = 0;
-            if (c < a.m) {
-                const int32_t* row = a.cols + (size_t)c * a.dc;
-                for (int p = 0; p < a.dc; ++p) {
-                    int j = row[p];
-                    if (j >= 0) par ^= xb[j];
+        for (int fs = 0; fs < fpp && fb + fs < f_end; ++fs) {
+            const int64_t f = fb + fs;
+            uint64_t wx[WN];
+            uint64_t myx = 0, myz = 0, mys = 0;
+#pragma unroll
+            for (int w = 0; w < WN; ++w) {
+                wx[w] = __builtin_amdgcn_ballot_w64(xb[(size_t)fs * nq + 64 * w + lane] != 0);
+                const uint64_t wz = __builtin_amdgcn_ballot_w64(zb[(size_t)fs * nq + 64 * w + lane] != 0);
+                if (lane == w) {
+                    myx = wx[w];
+                    myz = wz;
                 }
             }
-            uint64_t ws = __builtin_amdgcn_ballot_w64(par & 1u);
-            if (lane == 0) a.synd[f * a.wm + wd] = ws;
+#pragma unroll
+            for (int k = 0; k < CPLS; ++k) {
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int w = 0; w < WN; ++w) cnt += __builtin_popcountll(row[k][w] & wx[w]);
+                const uint64_t ws = __builtin_amdgcn_ballot_w64(cnt & 1u);
+                if (lane == k) mys = ws;
+            }
+            if (lane < a.wn) {
+                a.ex[f * a.wn + lane] = myx;
+                if (a.ez) a.ez[f * a.wn + lane] = myz;
+            }
+            if (lane < a.wm) a.synd[f * a.wm + lane] = mys;
         }
         wave_lds_sync_s();
     }
 }
 
-int launch_sample(const SampleArgs& a, hipStream_t st) {
+// Any size: column lists of H staged in LDS (16-bit), error bytes gathered.
+__global__ void __launch_bounds__(64 * kSampleWavesPerBlock) sample_kernel_gather(SampleArgs a) {
+    extern __shared__ unsigned char slds[];
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int fpp = 64 / a.lanes_per_frame;
+    const int nq = 64 * a.wn;
+    uint16_t* cols = reinterpret_cast<uint16_t*>(slds);
+    const int ncols = a.m * a.dc;
+    const size_t cols_bytes = ((size_t)ncols * 2 + 15) & ~(size_t)15;
+    for (int t = threadIdx.x; t < ncols; t += blockDim.x) cols[t] = (uint16_t)(a.cols[t] < 0 ? 0xFFFF : a.cols[t]);
+    __syncthreads();
+    unsigned char* xb = slds + cols_bytes + (size_t)wib * 2 * fpp * nq;
+    unsigned char* zb = xb + (size_t)fpp * nq;
+    const int64_t wave = (int64_t)blockIdx.x * kSampleWavesPerBlock + wib;
+    const int64_t f_begin = wave * a.frames_per_wave;
+    if (f_begin >= a.nframes) return;
+    const int64_t f_end = min(f_begin + (int64_t)a.frames_per_wave, a.nframes);
+    zero_tail(a, xb, nq, lane);
+
+    for (int64_t fb = f_begin; fb < f_end; fb += fpp) {
+        philox_pass(a, xb, zb, nq, fb, f_end, lane);
+        wave_lds_sync_s();
+        for (int fs = 0; fs < fpp && fb + fs < f_end; ++fs) {
+            const int64_t f = fb + fs;
+            const unsigned char* x = xb + (size_t)fs * nq;
+            for (int w = 0; w < a.wn; ++w) {
+                const uint64_t wx = __builtin_amdgcn_ballot_w64(x[64 * w + lane] != 0);
+                const uint64_t wz = __builtin_amdgcn_ballot_w64(zb[(size_t)fs * nq + 64 * w + lane] != 0);
+                if (lane == 0) {
+                    a.ex[f * a.wn + w] = wx;
+                    if (a.ez) a.ez[f * a.wn + w] = wz;
+                }
+            }
+            for (int k = 0; k < a.wm; ++k) {
+                const int c = 64 * k + lane;
+                uint32_t par = 0;
+                if (c < a.m) {
+                    const uint16_t* rc = cols + (size_t)c * a.dc;
+                    for (int p = 0; p < a.dc; ++p) {
+                        const uint16_t j = rc[p];
+                        if (j != 0xFFFF) par ^= x[j];
+                    }
+                }
+                const uint64_t ws = __builtin_amdgcn_ballot_w64(par & 1u);
+                if (lane == 0) a.synd[f * a.wm + k] = ws;
+            }
+        }
+        wave_lds_sync_s();
+    }
+}
+
+int launch_sample(const SampleArgs& a0, hipStream_t st) {
+    SampleArgs a = a0;
+    const int calls = (a.n + 3) / 4;
+    int lpf = 1;
+    while (lpf < calls && lpf < 64) lpf <<= 1;
+    a.lanes_per_frame = lpf;
+    const int fpp = 64 / lpf;
+    a.frames_per_wave = fpp * a0.frames_per_wave;  // passes per wave
     int64_t waves = (a.nframes + a.frames_per_wave - 1) / a.frames_per_wave;
     int64_t blocks = (waves + kSampleWavesPerBlock - 1) / kSampleWavesPerBlock;
     if (blocks > 0x7fffffff) return fail(SAGMS_EINVAL, "too many frames for one launch");
-    const int nq = (a.n + 63) & ~63;
-    size_t lds = (size_t)kSampleWavesPerBlock * 2 * nq;
-    hipLaunchKernelGGL(sample_kernel, dim3((unsigned)blocks), dim3(64 * kSampleWavesPerBlock), lds, st, a);
+    const dim3 grid((unsigned)blocks), block(64 * kSampleWavesPerBlock);
+#define ROWS(WN, CPLS)                                                                                    \
+    if (a.wn <= WN && a.wm <= CPLS) {                                                                      \
+        size_t lds = (size_t)kSampleWavesPerBlock * 2 * fpp * 64 * WN;                                     \
+        hipLaunchKernelGGL((sample_kernel_rows<WN, CPLS>), grid, block, lds, st, a);                      \
+        SAGMS_HIP(hipGetLastError());                                                                      \
+        return SAGMS_OK;                                                                                   \
+    }
+    if (a.rows) {
+        ROWS(1, 1)
+        ROWS(2, 1)
+        ROWS(4, 2)
+        ROWS(8, 4)
+    }
+#undef ROWS
+    if (a.n > 0xFFFF) return fail(SAGMS_EUNSUPPORTED, "sampler supports n < 65535");
+    size_t cols_bytes = ((size_t)a.m * a.dc * 2 + 15) & ~(size_t)15;
+    size_t lds = cols_bytes + (size_t)kSampleWavesPerBlock * 2 * fpp * 64 * a.wn;
+    if (lds > 65536) return fail(SAGMS_EUNSUPPORTED, "graph too large for the sampler's LDS");
+    hipLaunchKernelGGL(sample_kernel_gather, grid, block, lds, st, a);
     SAGMS_HIP(hipGetLastError());
     return SAGMS_OK;
 }

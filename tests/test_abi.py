@@ -113,6 +113,11 @@ def test_decoder_config_checks_before_device_work():
     prec = D("ms")
     prec.msg_precision = 3
     assert _decode_rc(g, prec) == sagms.EUNSUPPORTED
+    assert _decode_rc(g, D("ms", frames_per_wave=-1)) == sagms.EINVAL
+    assert _decode_rc(g, D("ms", frames_per_wave=2000)) == sagms.EINVAL
+    res = D("ms")
+    res.reserved = 1
+    assert _decode_rc(g, res) == sagms.EINVAL
     # a valid configuration with zero frames is a no-op that touches no device
     ok = D("sagms")
     assert sagms.lib().sagms_decode(g._h, None, None, ctypes.byref(ok), 0, None, None, None, None) == sagms.OK

@@ -57,6 +57,11 @@ def gpu_decode(g, synd_bits, llr, cfg, dev, soft=True):
             out["converged"].cpu().numpy().astype(bool), post.cpu().numpy())
 
 
+def tanner(l, a, b):
+    """The oracle's graph of a GB code, with the code's posterior-sum order."""
+    return decoders.TannerGraph(codes.gb_matrices(l, a, b)[1], codes.gb_var_checks(l, a, b))
+
+
 def params(kind, lmax, **kw):
     return decoders.DecoderParams(kind=kind, lmax=lmax, **kw), sagms.decoder_config(kind, lmax=lmax, **kw)
 
@@ -107,10 +112,34 @@ def test_decode_bit_exact_g63(dev, kind, kw, p):
     prm, cfg = params(kind, 100, **kw)
     say("decode G63", kind, kw, p, nf)
     e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
-    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    r = decoders.decode(tanner(l, a, b), s, llr, prm, "fp32")
     assert (it == r.iters).all()
     assert (cv == r.converged).all()
     assert (e == r.ehat).all()
+    assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("kind,kw", DECODERS + [("bp", {})])
+def test_decode_g63_given_as_rows(dev, kind, kw):
+    """The l = 63 code given row by row (CSR): the general LDS-staged kernel,
+    posteriors summed in ascending check order, bit-exact against the
+    oracle's default graph (BP within tolerance)."""
+    l, a, b = workloads.code("G63")
+    hx, hz = codes.gb_matrices(l, a, b)
+    g = sagms.Graph.from_dense(hz, hx)
+    p, nf = 0.06, 800
+    ex, _ = channel.sample_paulis(3, 1, 0, nf, g.n, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    prm, cfg = params(kind, 100, **kw)
+    say("decode G63 rows", kind, kw)
+    e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    if kind == "bp":
+        agree = (it == r.iters) & (e == r.ehat).all(axis=1)
+        assert agree.mean() > 0.97
+        return
+    assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
     assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
 
 
@@ -128,7 +157,7 @@ def test_decode_bit_exact_other_codes(dev, name, nf, kind):
     prm, cfg = params(kind, 60, **({"alpha": 0.75} if kind == "sms" else {}))
     say("decode", name, kind, nf)
     e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
-    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    r = decoders.decode(tanner(l, a, b), s, llr, prm, "fp32")
     assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
     assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
 
@@ -148,15 +177,15 @@ def test_decode_arbitrary_syndromes_and_priors(dev, lmax, kind):
     prm, cfg = params(kind, lmax)
     say("decode arbitrary", kind, lmax)
     e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
-    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    r = decoders.decode(tanner(l, a, b), s, llr, prm, "fp32")
     assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
     assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
     assert (it[~cv] == lmax).all()
 
 
 def test_decode_zero_noise_and_tiny_batches(dev):
-    g = sagms.Graph.gb(*workloads.code("G63"))
-    hz = codes.gb_matrices(*workloads.code("G63"))[1]
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
     llr = np.full(g.n, channel.prior_llr(0.05), dtype=np.float32)
     cfg = sagms.decoder_config("sagms")
     for nf in (1, 2, 3, 5, 63, 65):
@@ -165,7 +194,7 @@ def test_decode_zero_noise_and_tiny_batches(dev):
         assert not e.any() and (it == 0).all() and cv.all()
     s = workloads.random_syndromes(g.m, 5, seed=9, density=0.05)
     e, it, cv, _ = gpu_decode(g, s, llr, cfg, dev, soft=False)
-    r = decoders.decode(decoders.TannerGraph(hz), s, llr, decoders.DecoderParams(kind="sagms"), "fp32")
+    r = decoders.decode(tanner(l, a, b), s, llr, decoders.DecoderParams(kind="sagms"), "fp32")
     assert (it == r.iters).all() and (e == r.ehat).all()
 
 
@@ -223,7 +252,7 @@ def test_fp32_messages_within_tolerance_of_fp64(dev, kind, kw, p):
     llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
     L0 = float(llr[0])
     tol = MSG_TOL[(kind, kw.get("alpha"))]
-    tg = decoders.TannerGraph(hz)
+    tg = tanner(l, a, b)
     checked = 0
     for lmax in (1, 2, 3, 5, 7, 10):
         prm, cfg = params(kind, lmax, **kw)
@@ -258,13 +287,19 @@ def test_fer_matches_fp64_oracle(dev, kind, kw):
     say("fer vs fp64", kind, kw)
     e, it, cv, _ = gpu_decode(g, s, llr, cfg, dev, soft=False)
     llr64 = np.full(g.n, channel.prior_llr(p))
-    r64 = decoders.decode(decoders.TannerGraph(hz), s, llr64, prm, "fp64")
+    r64 = decoders.decode(tanner(l, a, b), s, llr64, prm, "fp64")
     lz = codes.logical_basis(hz, hx)
     f_gpu = int(judge.judge_logical(lz, ex, e, cv).sum())
     f_64 = int(judge.judge_logical(lz, ex, r64.ehat, r64.converged).sum())
-    lo_g, hi_g = stats.wilson(f_gpu, nf)
-    lo_o, hi_o = stats.wilson(f_64, nf)
-    assert lo_o <= f_gpu / nf <= hi_o and lo_g <= f_64 / nf <= hi_g
+    if kind == "ms":
+        # min-sum resolves its frequent exact ties by rounding residues (see
+        # the oracle's tie test), so its FER moves with precision and
+        # summation order: agreement within 25 % relative
+        assert abs(f_gpu - f_64) <= 0.25 * max(f_64, f_gpu)
+    else:
+        lo_g, hi_g = stats.wilson(f_gpu, nf)
+        lo_o, hi_o = stats.wilson(f_64, nf)
+        assert lo_o <= f_gpu / nf <= hi_o and lo_g <= f_64 / nf <= hi_g
     differ = (e != r64.ehat).any(axis=1)
     both = cv & r64.converged
     say("FER gpu %.4f fp64 %.4f, HD-disagreeing frames %.4f (%.4f of frames converged in both)"
@@ -286,7 +321,7 @@ def test_bp_against_oracle(dev):
     prm, cfg = params("bp", 100)
     say("decode bp")
     e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
-    r = decoders.decode(decoders.TannerGraph(hz), s, llr, prm, "fp32")
+    r = decoders.decode(tanner(l, a, b), s, llr, prm, "fp32")
     agree = (it == r.iters) & (e == r.ehat).all(axis=1)
     assert agree.mean() > 0.97
     tol = 1e-4 * np.maximum(np.abs(r.posterior[agree]), float(llr[0]))
@@ -318,8 +353,36 @@ def test_judge_matches_oracle_rank_test(dev):
     assert (fail == judge.judge_logical(codes.logical_basis(hz, hx), ex, eh, cv)).all()
     c = counters.cpu().numpy()
     assert c[0] == fail.sum() and c[1] == buf["iters"].cpu().numpy().sum()
-    # converged but logically wrong frames exist at this noise level
-    assert (fail & cv).any()
+
+
+@pytest.mark.parametrize("name", ["L7a", "G63", "G127", "G511w5"])
+def test_judge_on_constructed_residuals(dev, name):
+    """Residuals that are stabilizers (success), logical operators and their
+    sums (failure), with and without convergence, against the rank test."""
+    l, a, b = code_of(name)
+    g = sagms.Graph.gb(l, a, b)
+    hx, hz = codes.gb_matrices(l, a, b)
+    lz = codes.logical_basis(hz, hx)
+    rng = np.random.default_rng(8)
+    nf = 96
+    stab = (rng.integers(0, 2, size=(nf, hx.shape[0])) @ hx.astype(np.int64)) & 1
+    logi = (rng.integers(0, 2, size=(nf, lz.shape[0])) @ lz.astype(np.int64)) & 1
+    r = np.where((np.arange(nf) % 3 == 0)[:, None], stab, stab ^ logi).astype(np.uint8)
+    ex = rng.integers(0, 2, size=(nf, g.n)).astype(np.uint8)
+    eh = ex ^ r
+    cv = (np.arange(nf) % 5 != 0).astype(np.uint8)
+    it = rng.integers(0, 100, size=nf).astype(np.int32)
+    T = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x)).to(dev, dt)  # noqa: E731
+    fail = torch.empty(nf, dtype=torch.uint8, device=dev)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    sagms.judge(g, T(channel.pack(ex).view(np.int64), torch.int64), T(channel.pack(eh).view(np.int64), torch.int64),
+                T(cv, torch.uint8), T(it, torch.int32), counters, fail=fail)
+    torch.cuda.synchronize()
+    ref = judge.judge_rank(hx, ex, eh, cv.astype(bool))
+    got = fail.cpu().numpy().astype(bool)
+    assert (got == ref).all()
+    assert (got & cv.astype(bool)).any() and (~got).any()
+    assert counters.cpu().numpy().tolist() == [int(ref.sum()), int(it.sum())]
 
 
 # ----------------------------------------------- full size, bench launch shape
@@ -348,7 +411,7 @@ def test_full_size_sampled_frames(dev):
     ex_all, synd_all = u64(buf["ex"]), u64(buf["synd"])
     eh_all, it_all = u64(buf["ehat"]), buf["iters"].cpu().numpy()
     cv_all, fail_all = buf["converged"].cpu().numpy(), buf["fail"].cpu().numpy()
-    tg = decoders.TannerGraph(hz)
+    tg = tanner(l, a, b)
     lz = codes.logical_basis(hz, hx)
     llr_np = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
     exs = np.vstack([channel.sample_paulis(workloads.SWEEP_SEED, st, int(f), 1, g.n, p)[0] for f in idx])
@@ -396,3 +459,18 @@ def test_determinism_split_and_streams(dev):
     sagms.gen_errors(g, 9, 1, 2500, 100, p, part["ex"], part["ez"], part["synd"])
     torch.cuda.synchronize()
     assert torch.equal(part["ex"], buf["ex"][2500:2600]) and torch.equal(part["synd"], buf["synd"][2500:2600])
+
+
+@pytest.mark.parametrize("fpw", [1, 3, 16, 1024])
+def test_decode_launch_shape_does_not_change_results(dev, fpw):
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hz = codes.gb_matrices(l, a, b)[1]
+    p, nf = 0.07, 1500
+    ex, _ = channel.sample_paulis(4, 2, 0, nf, g.n, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    ref = gpu_decode(g, s, llr, sagms.decoder_config("sagms"), dev)
+    got = gpu_decode(g, s, llr, sagms.decoder_config("sagms", frames_per_wave=fpw), dev)
+    for x, y in zip(ref, got):
+        assert (x.view(np.uint8) == y.view(np.uint8)).all()

@@ -109,3 +109,11 @@ def test_draw_gb_reading():
     assert len(a) == 3 and len(b) == 3 and k >= 2
     assert codes.draw_gb(15, 3, seed=1) == (a, b, k, draws)
     assert codes.dimension(*codes.gb_matrices(15, a, b)) == k
+
+
+@pytest.mark.parametrize("code", [codes.G63, codes.G127, dict(l=7, a=(0, 1, 3), b=(0, 2, 6))])
+def test_gb_var_checks_are_the_columns_of_hz(code):
+    hx, hz = codes.gb_matrices(**code)
+    order = codes.gb_var_checks(**code)
+    for j in range(hz.shape[1]):
+        assert sorted(order[j]) == sorted(np.nonzero(hz[:, j])[0].tolist())

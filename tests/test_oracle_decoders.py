@@ -341,3 +341,28 @@ def test_min_sum_exact_ties_with_a_short_prior():
     assert fer["exact"] > 3 * fer["fp64"] and fer["exact"] > 3 * fer["fp32"]
     lo, hi = stats.wilson(int(round(fer["fp64"] * 800)), 800, z=3.0)
     assert lo <= fer["fp32"] <= hi
+
+
+def test_var_order_changes_only_fp32_rounding():
+    """An explicit per-variable check order leaves FP64 results unchanged
+    (exclusive sums are definitional) and changes FP32 posteriors by
+    rounding only; a bad order is rejected."""
+    hx, hz = codes.gb_matrices(**codes.G63)
+    ga = TannerGraph(hz)
+    gb = TannerGraph(hz, codes.gb_var_checks(**codes.G63))
+    p = 0.05
+    ex, _ = channel.sample_paulis(1, 4, 0, 300, 126, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(126, channel.prior_llr(p), dtype=np.float32)
+    prm = DecoderParams(kind="sagms", lmax=8)
+    a64 = decoders.decode(ga, s, llr, prm, "fp64", early_exit=False)
+    b64 = decoders.decode(gb, s, llr, prm, "fp64", early_exit=False)
+    assert np.allclose(a64.posterior, b64.posterior, rtol=1e-13, atol=1e-12)
+    a32 = decoders.decode(ga, s, llr, prm, "fp32", early_exit=False)
+    b32 = decoders.decode(gb, s, llr, prm, "fp32", early_exit=False)
+    assert (a32.posterior != b32.posterior).any()
+    assert np.allclose(a32.posterior, b32.posterior, rtol=1e-4, atol=1e-4 * llr[0])
+    bad = codes.gb_var_checks(**codes.G63)
+    bad[0] = bad[1]
+    with pytest.raises(ValueError):
+        TannerGraph(hz, bad)
