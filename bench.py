@@ -27,9 +27,42 @@ if ROOT not in sys.path:
 # figure counts an FMA as 2 flops and packed FP32 as 2 lanes).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # Algorithmic VALU cost of one edge-update (one c2v message produced on one
-# edge in one executed round), fixed from the paper's per-output operation
-# model restated for a wavefront implementation (see the design notes).
-OPS_PER_EDGE_UPDATE = 14
+# edge in one executed round), in 32-bit lane operations on gfx950 (3-input
+# med3 / bit operations available): v2c = posterior - c2v (1), running
+# minimum (1), second minimum by med3 (1), sign parity (1/2: one 3-input XOR
+# per two edges), hard-decision parity (1/2), output compare + select (2),
+# sign application (1), posterior accumulation (1).  Per-check work (two
+# gain products) and per-frame work are not counted.
+OPS_PER_EDGE_UPDATE = 8
+# HBM traffic of the decode kernel measured with rocprofv3 (FETCH_SIZE and
+# WRITE_SIZE, KiB per dispatch) and the copy-kernel calibration; used only
+# while the kernel source is unchanged since the counters were taken.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_g63_sagms_p005_traffic.json")
+DECODE_SOURCE = os.path.join(ROOT, "paper_2605_10433_amd", "csrc", "decode.hip")
+
+
+def measured_traffic(frames, p):
+    """HBM bytes per decode launch from the committed counter record, or None."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    sha = hashlib.sha256(open(DECODE_SOURCE, "rb").read()).hexdigest()
+    if rec.get("decode_source_sha256") != sha or rec.get("frames_per_launch") != frames or rec.get("p") != p:
+        return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+
+
+def copy_calibration(nbytes=1 << 30, reps=4):
+    """A plain device copy of known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters: each dispatch reads and writes nbytes."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": nbytes, "dispatches": reps}), flush=True)
 
 
 def cpu_baseline(p, lmax, params, frames=1 << 13):
@@ -80,7 +113,12 @@ def main():
                          "from the rows of H_Z (ascending check order)")
     ap.add_argument("--frames-per-wave", type=int, default=0, help="decode launch shape (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (traffic-counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the decoder is data-parallel over frames and a multi-GPU run "
               "would only split the frame range (see the design notes); run with --gpus 1", file=sys.stderr)
@@ -171,7 +209,8 @@ def main():
         "fer_wilson95": [lo, hi],
         "wall_s": wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": measured_traffic(nf, p) if args.graph == "gb" and args.decoder == "sagms" else None,
                      "kernel": kernel,
                      "ops_per_edge_update": OPS_PER_EDGE_UPDATE},
     }
