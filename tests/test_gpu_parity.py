@@ -474,3 +474,54 @@ def test_decode_launch_shape_does_not_change_results(dev, fpw):
     got = gpu_decode(g, s, llr, sagms.decoder_config("sagms", frames_per_wave=fpw), dev)
     for x, y in zip(ref, got):
         assert (x.view(np.uint8) == y.view(np.uint8)).all()
+
+
+C1 = None
+
+
+def c1_golden():
+    import base64
+    import json
+    import os
+    global C1
+    if C1 is None:
+        C1 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_calibration.json")))
+    dec = lambda s, n: np.frombuffer(base64.b64decode(s), dtype=np.uint8)[:n]  # noqa: E731
+    return C1, dec
+
+
+@pytest.mark.parametrize("name", ["ms", "sms", "sagms"])
+def test_cpu_calibration_case(dev, name):
+    """The CPU calibration case (l = 63, p = 0.05, seed 1 / stream 0, frames
+    0..9999, l_max = 50): the GPU agrees frame by frame with the stored FP32
+    oracle run and, for SMS / SAGMS, its FER lies in the Wilson interval of
+    the stored FP64 run.  Min-sum breaks its exact ties only as rounding
+    residues grow, which FP64 needs more rounds for, so its FP64 FER at
+    l_max = 50 is far higher (recorded, not a parity target)."""
+    c, dec = c1_golden()
+    d = c["decoders"][name]
+    l, a, b = workloads.code(c["code"])
+    g = sagms.Graph.gb(l, a, b)
+    nf = c["frames"]
+    buf = sagms.frame_buffers(g, nf, device=dev)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    sagms.gen_errors(g, c["seed"], c["stream"], 0, nf, c["p"], buf["ex"], buf["ez"], buf["synd"])
+    llr = torch.full((g.n,), float(np.float32(channel.prior_llr(c["p"]))), device=dev)
+    cfg = sagms.decoder_config(lmax=c["lmax"], **d["params"])
+    sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
+    sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters, fail=buf["fail"])
+    torch.cuda.synchronize()
+    fail = buf["fail"].cpu().numpy()
+    it = buf["iters"].cpu().numpy()
+    ref32 = np.unpackbits(dec(d["fp32"]["fail_bits"], (nf + 7) // 8))[:nf]
+    assert (fail == ref32).all()
+    assert (it == dec(d["fp32"]["iters"], nf)).all()
+    assert counters.cpu().numpy().tolist() == [d["fp32"]["failures"], d["fp32"]["sum_iters"]]
+    f64 = d["fp64"]["failures"]
+    if name == "ms":
+        assert f64 > 2 * int(fail.sum())
+    else:
+        lo, hi = stats.wilson(f64, nf)
+        assert lo <= fail.sum() / nf <= hi
+        lo, hi = stats.wilson(int(fail.sum()), nf)
+        assert lo <= f64 / nf <= hi
