@@ -52,8 +52,19 @@ typedef enum {
 
 typedef enum { SAGMS_FLOODING = 0 } sagms_schedule;
 
+/* Message formats (posteriors are always FP32 sums of the messages):
+ *   FP32  FP32 messages; BP evaluates its CN in FP64
+ *   FP16  every v2c / c2v message saturated to +-65504 and rounded to IEEE
+ *         half (nearest even): v2c = half(posterior - c2v), CN output =
+ *         sign * half(gain * min) with the product in FP32
+ *   INT6  sign + 6-bit magnitude on a grid of step 1/4 (+-15.75): q(x) =
+ *         clamp(nearest-even(4x), -63, 63) / 4 for every message and for
+ *         the prior, so posterior sums are exact
+ * FP16 / INT6 apply to MS, SMS and SAGMS (SAGMS_EUNSUPPORTED for BP). */
 typedef enum {
-    SAGMS_MSG_FP32 = 0 /* FP32 messages and sums; BP evaluates its CN in FP64 */
+    SAGMS_MSG_FP32 = 0,
+    SAGMS_MSG_FP16 = 1,
+    SAGMS_MSG_INT6 = 2
 } sagms_msg_precision;
 
 /* Decoder configuration (Algorithm 1 inputs besides H, s and L0).

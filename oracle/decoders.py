@@ -47,7 +47,19 @@ Arithmetic modes
             VN message = float32(posterior - own c2v)
           BP in this mode evaluates the CN in double from FP32 inputs and
           rounds the output to FP32.
-  Signed zeros of L0 are read as +0 in both modes.
+  "fp16"  reduced-precision messages with FP32 posteriors: every v2c and
+          c2v message is saturated to the largest finite half (+-65504) and
+          rounded to IEEE half (round to nearest even):
+            v2c       = half(posterior - c2v)       (FP32 difference)
+            CN output = sign * half(float32(gain) * exclusive min)
+            posterior = FP32 sum as in "fp32" (the first v2c is half(L0))
+  "int6"  6-bit magnitude plus sign on a grid of step 1/4 (range +-15.75):
+          q(x) = clip(round_half_even(4 x), -63, 63) / 4; the prior is
+          quantized too, L0' = q(L0), so posteriors L0' + sum c2v are exact
+            v2c       = q(posterior - c2v)          (saturating)
+            CN output = sign * q(float32(gain) * exclusive min)
+  The two quantized modes apply to the min-sum family only.
+  Signed zeros of L0 are read as +0 in all modes.
   The order of a variable's checks in the FP32 posterior sum is part of the
   graph: ascending check index by default, or an explicit order (for a GB
   code, the order of the terms of its polynomials; codes.gb_var_checks).
@@ -59,6 +71,17 @@ from dataclasses import dataclass
 import numpy as np
 
 KINDS = ("ms", "sms", "sagms", "bp")
+ARITH = ("fp64", "fp32", "fp16", "int6")
+
+
+def quantize(x, arith):
+    """The message rounding of a reduced-precision mode (identity otherwise)."""
+    x = np.asarray(x, dtype=np.float32)
+    if arith == "fp16":
+        return np.clip(x, -65504.0, 65504.0).astype(np.float16).astype(np.float32)
+    if arith == "int6":
+        return (np.clip(np.rint(x * np.float32(4.0)), -63.0, 63.0) * np.float32(0.25)).astype(np.float32)
+    return x
 # phi-form floor used by the BP check update (see module notes)
 BP_PHI_FLOOR = -np.log1p(-(2.0 ** -40))
 
@@ -149,13 +172,14 @@ def _neg(x):
     return x < 0
 
 
-def cn_minsum(v: np.ndarray, s: np.ndarray, gain: np.ndarray) -> np.ndarray:
+def cn_minsum(v: np.ndarray, s: np.ndarray, gain: np.ndarray, arith: str = "fp64") -> np.ndarray:
     """Eq. (ms_cn) / (sagms_cn) for every check position, by exclusion.
 
     v [F, m, d] incoming VN->CN messages (padding slots hold +inf),
     s [F, m] original syndrome bits, gain [F, m].  Returns [F, m, d]:
       out[p] = (-1)^s * prod_{q != p} sgn(v[q]) * gain * min_{q != p} |v[q]|.
-    The product gain * min is rounded in the dtype of `v`.
+    The product gain * min is rounded in the dtype of `v`, then to the
+    message format of `arith` ("fp16", "int6").
     """
     d = v.shape[-1]
     other = ~np.eye(d, dtype=bool)                       # [p, q]: q != p
@@ -164,6 +188,8 @@ def cn_minsum(v: np.ndarray, s: np.ndarray, gain: np.ndarray) -> np.ndarray:
     neg = _neg(v)
     par = ((neg[..., None, :] & other).sum(axis=-1) + s[..., None]) & 1
     out = gain.astype(v.dtype)[..., None] * excl_min
+    if arith in ("fp16", "int6"):
+        out = quantize(out, arith)
     return np.where(par.astype(bool), -out, out)
 
 
@@ -220,11 +246,15 @@ def decode(g: TannerGraph, synd, llr0, params: DecoderParams, arith: str = "fp64
                             np.concatenate([r.iters for r in parts]),
                             np.concatenate([r.converged for r in parts]),
                             np.concatenate([r.posterior for r in parts]))
-    if arith not in ("fp64", "fp32"):
-        raise ValueError("arith must be 'fp64' or 'fp32'")
+    if arith not in ARITH:
+        raise ValueError("arith must be one of %s" % (ARITH,))
+    if arith in ("fp16", "int6") and params.kind == "bp":
+        raise ValueError("reduced-precision messages apply to the min-sum family only")
     dt = np.float64 if arith == "fp64" else np.float32
     m, n, E = g.m, g.n, g.E
     L0 = np.asarray(llr0, dtype=np.float64).astype(dt) + dt(0.0)   # -0 -> +0
+    if arith == "int6":
+        L0 = quantize(L0, arith)
     if L0.shape != (n,):
         raise ValueError("llr0 must have n entries")
 
@@ -240,7 +270,7 @@ def decode(g: TannerGraph, synd, llr0, params: DecoderParams, arith: str = "fp64
 
     # message slots: E edges plus the padding sentinel
     v2c = np.empty((f, E + 1), dtype=dt)
-    v2c[:, :E] = L0[g.e_var]
+    v2c[:, :E] = quantize(L0[g.e_var], arith) if arith in ("fp16", "int6") else L0[g.e_var]
     v2c[:, E] = np.inf
     c2v = np.zeros((f, E + 1), dtype=dt)
     vn_valid = g.vn_edge < E
@@ -258,7 +288,7 @@ def decode(g: TannerGraph, synd, llr0, params: DecoderParams, arith: str = "fp64
         if params.kind == "bp":
             cout = cn_bp(vin, s_i)
         else:
-            cout = cn_minsum(vin, s_i, gain)
+            cout = cn_minsum(vin, s_i, gain, arith)
         cnew = np.zeros((idx.size, E + 1), dtype=dt)
         valid_c = g.cn_edge < E
         cnew[:, g.cn_edge[valid_c]] = cout[:, valid_c]
@@ -277,6 +307,8 @@ def decode(g: TannerGraph, synd, llr0, params: DecoderParams, arith: str = "fp64
             for r in range(g.vn_edge.shape[1]):               # ascending check order
                 post = np.where(vn_valid[None, :, r], post + cj[:, :, r], post)
             vnew[:, :E] = post[:, g.e_var] - cnew[:, :E]
+            if arith in ("fp16", "int6"):
+                vnew[:, :E] = quantize(vnew[:, :E], arith)
         # (iv) hard decision and (v) residual syndrome
         e = (post < 0).astype(np.uint8)
         r_new = s_i ^ (((e.astype(np.int64) @ g.h.T.astype(np.int64)) & 1).astype(np.uint8))

@@ -14,7 +14,10 @@ int check_cfg(const sagms_decoder_cfg* c) {
     if (!c) return fail(SAGMS_EINVAL, "cfg is null");
     if (c->kind < SAGMS_MS || c->kind > SAGMS_BP) return fail(SAGMS_EINVAL, "unknown decoder kind %d", c->kind);
     if (c->schedule != SAGMS_FLOODING) return fail(SAGMS_EUNSUPPORTED, "only the flooding schedule is implemented");
-    if (c->msg_precision != SAGMS_MSG_FP32) return fail(SAGMS_EUNSUPPORTED, "message precision %d not available", c->msg_precision);
+    if (c->msg_precision < SAGMS_MSG_FP32 || c->msg_precision > SAGMS_MSG_INT6)
+        return fail(SAGMS_EUNSUPPORTED, "message precision %d not available", c->msg_precision);
+    if (c->kind == SAGMS_BP && c->msg_precision != SAGMS_MSG_FP32)
+        return fail(SAGMS_EUNSUPPORTED, "BP runs with FP32 messages only");
     if (c->lmax < 1) return fail(SAGMS_EINVAL, "lmax must be >= 1 (got %d)", c->lmax);
     if (c->frames_per_wave < 0 || c->frames_per_wave > 1024)
         return fail(SAGMS_EINVAL, "frames_per_wave must lie in [0, 1024]");
@@ -120,7 +123,7 @@ int sagms_decode_soft(sagms_graph gh, const uint64_t* synd, const float* llr0, c
     a.lmax = cfg->lmax;
     a.frames_per_wave = cfg->frames_per_wave > 0 ? cfg->frames_per_wave : kDecodeFramesPerWave;
     a.L = g->layout;
-    return launch_decode(g->shape, cfg->kind == SAGMS_BP, a, 0, st);
+    return launch_decode(g->shape, cfg->kind == SAGMS_BP, cfg->msg_precision, a, st);
 }
 
 int sagms_judge(sagms_graph gh, const uint64_t* ex, const uint64_t* ehat, const uint8_t* converged,

@@ -25,6 +25,8 @@
 // Posteriors and v2c messages are never -0.0 (L0 is read as L0 + 0.0f and
 // every later value is a sum or a difference of finite floats starting from
 // it), so sign bits and "< 0" agree and the kernel uses sign bits.
+#include <hip/hip_fp16.h>
+
 #include "internal.h"
 
 namespace sagms {
@@ -98,11 +100,26 @@ __device__ __forceinline__ uint32_t xor_signs(const float (&x)[N], uint32_t init
     return acc & kSign;
 }
 
+// Message formats: FP32; FP16 (every message saturated to +-65504 and
+// rounded to half, posteriors FP32); INT6 (sign + 6-bit magnitude on a grid
+// of step 1/4, saturating at +-63 steps; the prior is quantized as well, so
+// posterior sums are exact).  Messages are held as FP32 values on the grid.
+template <int MT>
+__device__ __forceinline__ float quantize(float x) {
+    if constexpr (MT == SAGMS_MSG_FP16) {
+        return __half2float(__float2half_rn(__builtin_amdgcn_fmed3f(x, -65504.0f, 65504.0f)));
+    } else if constexpr (MT == SAGMS_MSG_INT6) {
+        return __builtin_amdgcn_fmed3f(rintf(x * 4.0f), -63.0f, 63.0f) * 0.25f;
+    } else {
+        return x;
+    }
+}
+
 // Check-node update of one check (eq. (ms_cn) scaled per eq. (alphaeff) /
 // (sagms_cn), or eq. (bp4_cn) for BP): v = incoming v2c messages, sb = the
 // original syndrome bit, res = the residual bit (both at the sign position),
 // gs / gu = the gains of a satisfied / unsatisfied check.
-template <int DC, bool BP>
+template <int DC, bool BP, int MT>
 __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, uint32_t res, float gs, float gu,
                                           float (&c2v)[DC]) {
     const uint32_t par = xor_signs<DC>(v, sb);
@@ -124,7 +141,7 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, uin
         // parity; per edge: compare, select, and one 3-input bit operation
         // applying the edge's own sign.  The empty asm keeps the compiler
         // from folding the select back into one product per edge.
-        uint32_t S1 = bits(alpha * m1) | par, S2 = bits(alpha * m2) | par;
+        uint32_t S1 = bits(quantize<MT>(alpha * m1)) | par, S2 = bits(quantize<MT>(alpha * m2)) | par;
         asm("" : "+v"(S1), "+v"(S2));
 #pragma unroll
         for (int p = 0; p < DC; ++p) {
@@ -134,7 +151,7 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, uin
     }
 }
 
-template <int DC, int DV, int CPL, int VPL, bool BP>
+template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs a) {
     using LY = Lay<DC, CPL, VPL>;
     extern __shared__ float lds_all[];
@@ -161,7 +178,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
 #pragma unroll
     for (int k = 0; k < VPL; ++k) {
         int j = k * 64 + lane;
-        L0[k] = j < a.n ? a.llr0[j] + 0.0f : __builtin_inff();
+        L0[k] = j < a.n ? quantize<MT == SAGMS_MSG_INT6 ? MT : SAGMS_MSG_FP32>(a.llr0[j] + 0.0f) : __builtin_inff();
     }
     // gain table: in registers (lane w holds entry w) when m <= 64, else in LDS
     const float gsl = a.gains[2 * lane], gul = a.gains[2 * lane + 1];
@@ -208,7 +225,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
 #pragma unroll
                 for (int p = 0; p < DC; ++p) {
                     pj[p] = lds[caddr[k][p]];
-                    v[k][p] = pj[p] - c2v[k][p];
+                    v[k][p] = quantize<MT>(pj[p] - c2v[k][p]);
                 }
                 res[k] = xor_signs<DC>(pj, sb[k]);
                 w += __builtin_popcountll(ballot(res[k] != 0));
@@ -231,7 +248,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
             }
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
-                cn_update<DC, BP>(v[k], sb[k], res[k], gs, gu, c2v[k]);
+                cn_update<DC, BP, MT>(v[k], sb[k], res[k], gs, gu, c2v[k]);
 #pragma unroll
                 for (int p = 0; p < DC; ++p) lds[p * LY::CW + k * 64 + lane] = c2v[k][p];
             }
@@ -277,8 +294,13 @@ static int waves_per_block(const DecodeLayout& L) {
     return w < 1 ? 1 : (w > kWavesPerBlock ? kWavesPerBlock : w);
 }
 
+template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
+static void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const DecodeArgs& a) {
+    hipLaunchKernelGGL((decode_kernel<DC, DV, CPL, VPL, BP, MT>), grid, block, lds, st, a);
+}
+
 template <int DC, int DV, int CPL, int VPL>
-static int launch_shape(bool bp, const DecodeArgs& a, hipStream_t st) {
+static int launch_shape(bool bp, int mt, const DecodeArgs& a, hipStream_t st) {
     using LY = Lay<DC, CPL, VPL>;
     if (a.L.cw != LY::CW || a.L.zero != LY::ZERO || a.L.post0 != LY::POST0 || a.L.padpost != LY::PADPOST ||
         a.L.gain0 != LY::GAIN0 || a.L.words != LY::WORDS)
@@ -289,18 +311,22 @@ static int launch_shape(bool bp, const DecodeArgs& a, hipStream_t st) {
     int64_t blocks = (waves + wpb - 1) / wpb;
     if (blocks > 0x7fffffff) return fail(SAGMS_EINVAL, "too many frames for one launch");
     size_t lds = (size_t)wpb * a.L.words * sizeof(float);
+    const dim3 grid((unsigned)blocks), block(64 * wpb);
     if (bp)
-        hipLaunchKernelGGL((decode_kernel<DC, DV, CPL, VPL, true>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a);
+        launch_one<DC, DV, CPL, VPL, true, SAGMS_MSG_FP32>(grid, block, lds, st, a);
+    else if (mt == SAGMS_MSG_FP16)
+        launch_one<DC, DV, CPL, VPL, false, SAGMS_MSG_FP16>(grid, block, lds, st, a);
+    else if (mt == SAGMS_MSG_INT6)
+        launch_one<DC, DV, CPL, VPL, false, SAGMS_MSG_INT6>(grid, block, lds, st, a);
     else
-        hipLaunchKernelGGL((decode_kernel<DC, DV, CPL, VPL, false>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
-                           a);
+        launch_one<DC, DV, CPL, VPL, false, SAGMS_MSG_FP32>(grid, block, lds, st, a);
     SAGMS_HIP(hipGetLastError());
     return SAGMS_OK;
 }
 
-int launch_decode(const DecodeShape& s, bool bp, const DecodeArgs& a, int, hipStream_t st) {
+int launch_decode(const DecodeShape& s, bool bp, int mt, const DecodeArgs& a, hipStream_t st) {
 #define SHAPE(DC, DV, CPL, VPL) \
-    if (s.dc == DC && s.dv == DV && s.cpl == CPL && s.vpl == VPL) return launch_shape<DC, DV, CPL, VPL>(bp, a, st);
+    if (s.dc == DC && s.dv == DV && s.cpl == CPL && s.vpl == VPL) return launch_shape<DC, DV, CPL, VPL>(bp, mt, a, st);
     SHAPE(4, 2, 1, 1)
     SHAPE(6, 3, 1, 1)
     SHAPE(10, 5, 1, 2)

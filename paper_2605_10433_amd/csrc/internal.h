@@ -113,7 +113,7 @@ struct DecodeArgs {
     int m, n, wm, wn, lmax, frames_per_wave;
     DecodeLayout L;
 };
-int launch_decode(const DecodeShape& s, bool bp, const DecodeArgs& a, int waves_per_block, hipStream_t st);
+int launch_decode(const DecodeShape& s, bool bp, int msg_precision, const DecodeArgs& a, hipStream_t st);
 
 
 struct SampleArgs {

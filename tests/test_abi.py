@@ -113,6 +113,7 @@ def test_decoder_config_checks_before_device_work():
     prec = D("ms")
     prec.msg_precision = 3
     assert _decode_rc(g, prec) == sagms.EUNSUPPORTED
+    assert _decode_rc(g, D("bp", precision="fp16")) == sagms.EUNSUPPORTED
     assert _decode_rc(g, D("ms", frames_per_wave=-1)) == sagms.EINVAL
     assert _decode_rc(g, D("ms", frames_per_wave=2000)) == sagms.EINVAL
     res = D("ms")

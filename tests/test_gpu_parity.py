@@ -525,3 +525,56 @@ def test_cpu_calibration_case(dev, name):
         assert lo <= fail.sum() / nf <= hi
         lo, hi = stats.wilson(int(fail.sum()), nf)
         assert lo <= f64 / nf <= hi
+
+
+@pytest.mark.parametrize("precision", ["fp16", "int6"])
+@pytest.mark.parametrize("kind,kw", [("ms", {}), ("sms", dict(alpha=0.75)), ("sagms", {})])
+@pytest.mark.parametrize("p", [0.03, 0.05, 0.08])
+def test_reduced_precision_bit_exact(dev, precision, kind, kw, p):
+    """FP16 and INT6 messages: hard decisions, rounds, flags and FP32
+    posteriors bit-exact against the oracle's mode of the same format."""
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    hz = codes.gb_matrices(l, a, b)[1]
+    nf = 1000
+    ex, _ = channel.sample_paulis(1, workloads.stream_of(p), 0, nf, g.n, p)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(p), dtype=np.float32)
+    prm = decoders.DecoderParams(kind=kind, lmax=100, **kw)
+    cfg = sagms.decoder_config(kind, lmax=100, precision=precision, **kw)
+    say("decode", precision, kind, kw, p)
+    e, it, cv, post = gpu_decode(g, s, llr, cfg, dev)
+    r = decoders.decode(tanner(l, a, b), s, llr, prm, precision)
+    assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
+    assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("precision", ["fp16", "int6"])
+@pytest.mark.parametrize("name,nf", [("L7b", 300), ("G127", 300), ("G255w4", 150), ("G511w5", 40)])
+def test_reduced_precision_other_codes(dev, precision, name, nf):
+    l, a, b = code_of(name)
+    g = sagms.Graph.gb(l, a, b)
+    hz = codes.gb_matrices(l, a, b)[1]
+    ex, _ = channel.sample_paulis(6, 1, 0, nf, g.n, 0.04)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(g.n, channel.prior_llr(0.04), dtype=np.float32)
+    say("decode", precision, name)
+    e, it, cv, post = gpu_decode(g, s, llr, sagms.decoder_config("sagms", lmax=60, precision=precision), dev)
+    r = decoders.decode(tanner(l, a, b), s, llr, decoders.DecoderParams(kind="sagms", lmax=60), precision)
+    assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
+    assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("precision", ["fp16", "int6"])
+def test_reduced_precision_arbitrary_inputs(dev, precision):
+    l, a, b = workloads.code("G63")
+    g = sagms.Graph.gb(l, a, b)
+    s = workloads.random_syndromes(g.m, 300, seed=11)
+    rng = np.random.default_rng(12)
+    llr = rng.uniform(-2.0, 20.0, size=g.n).astype(np.float32)
+    llr[5] = -0.0
+    for lmax in (1, 9):
+        e, it, cv, post = gpu_decode(g, s, llr, sagms.decoder_config("ms", lmax=lmax, precision=precision), dev)
+        r = decoders.decode(tanner(l, a, b), s, llr, decoders.DecoderParams(kind="ms", lmax=lmax), precision)
+        assert (it == r.iters).all() and (e == r.ehat).all()
+        assert (post.view(np.uint32) == r.posterior.view(np.uint32)).all()

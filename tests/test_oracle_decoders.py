@@ -366,3 +366,47 @@ def test_var_order_changes_only_fp32_rounding():
     bad[0] = bad[1]
     with pytest.raises(ValueError):
         TannerGraph(hz, bad)
+
+
+def test_quantizers():
+    x = np.array([0.0, 0.1, 0.125, 0.375, 1.0 / 3, 15.74, 15.9, 100.0, -0.125, -0.375, -7.3], dtype=np.float32)
+    q6 = decoders.quantize(x, "int6")
+    assert q6.tolist() == [0.0, 0.0, 0.0, 0.5, 0.25, 15.75, 15.75, 15.75, -0.0, -0.5, -7.25]
+    assert (np.abs(q6) <= 15.75).all() and ((q6 * 4) == np.round(q6 * 4)).all()
+    q16 = decoders.quantize(x, "fp16")
+    assert (q16 == x.astype(np.float16).astype(np.float32)).all()
+    big = decoders.quantize(np.array([7e4, -1e30, np.float32(65519.0)], dtype=np.float32), "fp16")
+    assert big.tolist() == [65504.0, -65504.0, 65504.0]                          # saturating
+    assert decoders.quantize(np.float32(1 + 2 ** -11), "fp16") == 1.0          # ties to even
+    assert decoders.quantize(np.float32(1 + 3 * 2 ** -11), "fp16") == np.float32(1 + 2 ** -9)
+
+
+@pytest.mark.parametrize("arith", ["fp16", "int6"])
+def test_quantized_modes_track_fp32(g63_batch, arith):
+    """Reduced-precision messages: every message lies on the format's grid,
+    the FER stays close to FP32, and zero / invariant cases still hold."""
+    g, hz, s, llr = g63_batch
+    prm = DecoderParams(kind="sagms", lmax=40)
+    tr = decoders.decode(g, s[:100], llr, prm, arith, early_exit=False, trace=True)
+    for rd in tr.trace:
+        for key in ("c2v", "v2c"):
+            assert (decoders.quantize(rd[key], arith) == rd[key]).all()
+    r = decoders.decode(g, s, llr, prm, arith)
+    r32 = decoders.decode(g, s, llr, prm, "fp32")
+    assert abs(int(r.converged.sum()) - int(r32.converged.sum())) <= 0.1 * len(s)
+    resid = s ^ channel.syndrome(hz, r.ehat)
+    assert not resid[r.converged].any()
+    with pytest.raises(ValueError):
+        decoders.decode(g, s[:2], llr, DecoderParams(kind="bp"), arith)
+
+
+def test_int6_posteriors_are_exact_sums():
+    """int6: posteriors are sums of grid values, computed exactly in FP32."""
+    hx, hz = codes.gb_matrices(**codes.G63)
+    g = TannerGraph(hz)
+    ex, _ = channel.sample_paulis(2, 0, 0, 50, 126, 0.06)
+    s = channel.syndrome(hz, ex)
+    llr = np.full(126, channel.prior_llr(0.06), dtype=np.float32)
+    r = decoders.decode(g, s, llr, DecoderParams(kind="sms", alpha=0.75, lmax=12), "int6", trace=True)
+    for rd in r.trace:
+        assert ((rd["post"] * 4) == np.round(rd["post"] * 4)).all()
