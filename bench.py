@@ -98,13 +98,131 @@ def gb_dense(l, a, b):
     return np.hstack([B.T, A.T]), np.hstack([A, B])
 
 
+def run_mix(args):
+    """The mixed-code workload: 2^22 frames per step over four GB codes
+    (40 / 30 / 20 / 10 %), one sagms_batch_run per step."""
+    import torch
+
+    import paper_2605_10433_amd as sagms
+    import workloads
+    from paper_2605_10433_amd.stats import wilson
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = args.p if args.p is not None else workloads.MIX_P
+    cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, precision=args.precision,
+                               **workloads.SAGMS_PARAMS)
+    segs = []
+    for i, (name, nf) in enumerate(zip(workloads.MIX_CODES, workloads.MIX_FRAMES)):
+        g = sagms.Graph.gb(*workloads.code(name))
+        buf = sagms.frame_buffers(g, nf, device=dev, with_ez=False)
+        segs.append(dict(graph=g, name=name, nf=nf, synd=buf["synd"], ex=buf["ex"], ehat=buf["ehat"],
+                         iters=buf["iters"], converged=buf["converged"], stream_id=workloads.mix_stream(i, p),
+                         llr0=torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)))
+    batch = sagms.Batch(segs, cfg)
+    counters = torch.zeros((len(segs), 2), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def fill(s):
+        for sg in segs:
+            sagms.gen_errors(sg["graph"], workloads.MIX_SEED, sg["stream_id"], s * sg["nf"], sg["nf"], p, sg["ex"],
+                             None, sg["synd"])
+
+    tune_log = None
+    if args.tune:
+        fill(args.steps + args.warmup)
+        best, results = batch.tune(reps=3)
+        tune_log = sorted(results, key=lambda r: r[1])
+    elif args.plan:
+        batch.set_plan(sagms.plan(**json.loads(args.plan)))
+    if args.graph_launch:
+        batch.instantiate()
+
+    def step(s, ev=None):
+        fill(s)
+        if ev is not None:
+            ev[0].record(stream)
+        batch.run()
+        if ev is not None:
+            ev[1].record(stream)
+        for i, sg in enumerate(segs):
+            sagms.judge(sg["graph"], sg["ex"], sg["ehat"], sg["converged"], sg["iters"], counters[i])
+
+    for s in range(args.warmup):
+        step(args.steps + s)
+    torch.cuda.synchronize()
+    counters.zero_()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start.record(stream)
+    for s in range(args.steps):
+        step(s, events[s])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ms = t_start.elapsed_time(t_end)
+    dec_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in events]))
+    c = counters.cpu().numpy()
+    frames_step = sum(sg["nf"] for sg in segs)
+    frames = frames_step * args.steps
+    ops = sum(OPS_PER_EDGE_UPDATE * int(c[i, 1]) * sg["graph"].n_edges for i, sg in enumerate(segs)) / args.steps
+    achieved = ops / (dec_ms * 1e-3) / 1e12
+    per_code = {}
+    for i, sg in enumerate(segs):
+        n = sg["nf"] * args.steps
+        lo, hi = wilson(int(c[i, 0]), n)
+        per_code[sg["name"]] = {"frames_per_step": sg["nf"], "fer": int(c[i, 0]) / n, "fer_wilson95": [lo, hi],
+                                "mean_iters": int(c[i, 1]) / n}
+    plan = batch.get_plan().as_dict()
+    out = {
+        "metric": "%s frames/s" % args.decoder.upper(),
+        "value": frames / (total_ms * 1e-3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16 messages, f32 posteriors", "int6": "int6 messages"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "mixed GB codes %s at %s %% of %d Philox frames/step, code-capacity depolarizing "
+                               "p=%g, %s l_max=%d early exit, flooding, %s messages, one batch run per step"
+                               % ("/".join(workloads.MIX_CODES), "/".join("%g" % (100 * x) for x in workloads.MIX_SHARES),
+                                  frames_step, p, args.decoder.upper(), args.lmax, args.precision.upper()),
+                   "codes": workloads.MIX_CODES, "frames_per_step": workloads.MIX_FRAMES, "p": p,
+                   "decoder": args.decoder, "lmax": args.lmax, "precision": args.precision, "plan": plan,
+                   "graph_launch": bool(args.graph_launch), "tuned": bool(args.tune)},
+        "decode_ms_per_step": dec_ms,
+        "decode_frames_per_s": frames_step / (dec_ms * 1e-3),
+        "per_code": per_code,
+        "wall_s": wall,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "batch run (%s plan)" % plan["kind"], "ops_per_edge_update": OPS_PER_EDGE_UPDATE},
+    }
+    if tune_log is not None:
+        out["tune"] = [{"plan": pl, "ms": ms} for pl, ms in tune_log]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1 << 20)
-    ap.add_argument("--p", type=float, default=0.05)
+    ap.add_argument("--p", type=float, default=None, help="noise level (default 0.05; 0.04 for the mix)")
+    ap.add_argument("--workload", default="g63", choices=["g63", "mix"],
+                    help="g63: the l = 63 code, 2^20 frames per step; mix: four GB codes, 2^22 frames per step "
+                         "in one batch")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "int6"], help="message format (mix)")
+    ap.add_argument("--plan", default="", help="mix: launch plan as JSON, e.g. '{\"kind\": \"tiered\"}'")
+    ap.add_argument("--tune", action="store_true", help="mix: run the plan autotuner before timing")
+    ap.add_argument("--graph-launch", action="store_true", help="mix: replay the batch as a HIP graph")
     ap.add_argument("--decoder", default="sagms", choices=["ms", "sms", "sagms", "bp"])
     ap.add_argument("--alpha", type=float, default=0.75)
     ap.add_argument("--lmax", type=int, default=100)
@@ -124,6 +242,11 @@ def main():
               "would only split the frame range (see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "mix":
+        run_mix(args)
+        return
+    if args.p is None:
+        args.p = 0.05
     import torch
 
     import paper_2605_10433_amd as sagms

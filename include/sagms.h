@@ -199,6 +199,97 @@ int sagms_decode_soft(sagms_graph g, const uint64_t* synd, const float* llr0, co
 int sagms_judge(sagms_graph g, const uint64_t* ex, const uint64_t* ehat, const uint8_t* converged,
                 const int32_t* iters, int64_t nframes, uint8_t* fail, uint64_t* counters, void* stream);
 
+/* ---- mixed-code batches ------------------------------------------------
+ * A batch decodes, in one call, several runs of frames ("segments"), each of
+ * its own code: the same Algorithm 1 as sagms_decode, with one decoder
+ * configuration for all segments.  Every frame's outputs equal those of
+ * sagms_decode on that segment alone, bit for bit, whatever the plan, the
+ * mix or the order in which frames run.  The buffers are bound when the
+ * batch is created (device pointers of the device current at creation); the
+ * caller refills the syndromes and calls sagms_batch_run again. */
+
+typedef struct sagms_batch_s* sagms_batch;
+
+typedef struct {
+    sagms_graph graph;         /* code of the segment                            */
+    const uint64_t* synd;      /* device [nframes][words_m]                      */
+    const float* llr0;         /* device [n]                                     */
+    int64_t nframes;           /* >= 0                                           */
+    uint64_t* ehat;            /* device [nframes][words_n]                      */
+    int32_t* iters;            /* device [nframes]                               */
+    uint8_t* converged;        /* device [nframes]                               */
+    float* posterior;          /* device [nframes][n], or NULL                   */
+} sagms_segment;
+
+/* How a batch is launched.
+ *   SINGLE    one persistent kernel over all segments: waves take tiles of
+ *             tile_frames frames from work queues until all are done (the
+ *             kernel's registers are those of the largest code's shape)
+ *   TIERED    one persistent kernel per register class of the codes, in
+ *             stream order from the largest class down
+ *   PER_CODE  one sagms_decode launch per segment, tile_frames frames per
+ *             wave
+ * waves_per_block (1, 2 or 4), blocks_per_cu (0 = as many as fit, else
+ * 1..64) and reg_budget (0 = the compiler's register allocation, 1 = a
+ * tighter one allowing one more resident wave per SIMD for the register
+ * classes that have one compiled, the compiler's for the others) apply to
+ * the persistent plans; a code class whose LDS slices would exceed 64 KiB
+ * per block runs with waves_per_block halved until they fit.  Results never
+ * depend on the plan. */
+typedef enum { SAGMS_PLAN_SINGLE = 0, SAGMS_PLAN_TIERED = 1, SAGMS_PLAN_PER_CODE = 2 } sagms_plan_kind;
+
+typedef struct {
+    int32_t kind;            /* sagms_plan_kind     */
+    int32_t tile_frames;     /* 1 .. 1024           */
+    int32_t waves_per_block;
+    int32_t blocks_per_cu;
+    int32_t reg_budget;
+    int32_t reserved;        /* must be 0           */
+} sagms_plan;
+
+typedef struct {
+    sagms_plan plan;
+    float ms;                /* median time of one run, milliseconds */
+} sagms_tune_result;
+
+/* Creates a batch of nseg (1..16) segments for decoder cfg (MS, SMS or
+ * SAGMS; BP is SAGMS_EUNSUPPORTED).  Checks every argument (SAGMS_EINVAL),
+ * uploads the graphs' tables to the current device and synchronizes it.
+ * The initial plan is SINGLE with tile_frames 8, waves_per_block 4,
+ * blocks_per_cu 0 and reg_budget 0.  The batch keeps its own copy of cfg
+ * and of the segment table; the graphs must outlive it. */
+int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_decoder_cfg* cfg, sagms_batch* out);
+
+/* Replaces the plan (checked as described at sagms_plan; SAGMS_EINVAL) and
+ * drops an instantiated graph. */
+int sagms_batch_set_plan(sagms_batch b, const sagms_plan* plan);
+int sagms_batch_get_plan(sagms_batch b, sagms_plan* plan);
+
+/* Enqueues one decode of every segment on `stream` (NULL = the null
+ * stream): the instantiated graph if there is one, else the plan's kernels.
+ * Calls that overlap in time on one batch race on its work queues: order
+ * them on one stream. */
+int sagms_batch_run(sagms_batch b, void* stream);
+
+/* Captures the current plan's launches (queue reset and kernels, no memset
+ * or copy nodes) into a HIP graph and instantiates it; later
+ * sagms_batch_run calls launch the graph.  Host call, not stream-ordered. */
+int sagms_batch_instantiate(sagms_batch b);
+
+/* Autotuner: times every candidate plan (SINGLE, and TIERED when the codes
+ * fall in more than one register class, with tile_frames in {4, 8, 16, 32},
+ * waves_per_block in {1, 2, 4} and both register budgets where they differ;
+ * PER_CODE with tile_frames in {4, 8, 16, 32}) on the batch's own
+ * buffers, `reps` (1..100) timed runs each after one warm-up run, keeps the
+ * plan with the smallest median time and returns it in *best (may be NULL).
+ * Up to `cap` results go to results (may be NULL), their number to *count
+ * (may be NULL).  The runs overwrite the batch's outputs; the stream is
+ * synchronized on return. */
+int sagms_batch_tune(sagms_batch b, void* stream, int32_t reps, sagms_tune_result* results, int32_t cap,
+                     int32_t* count, sagms_plan* best);
+
+int sagms_batch_destroy(sagms_batch b);
+
 /* Message for the last non-zero status returned on this thread. */
 const char* sagms_last_error(void);
 

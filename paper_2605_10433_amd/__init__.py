@@ -42,6 +42,35 @@ class DecoderConfig(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class Segment(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("synd", ctypes.c_void_p), ("llr0", ctypes.c_void_p),
+                ("nframes", ctypes.c_int64), ("ehat", ctypes.c_void_p), ("iters", ctypes.c_void_p),
+                ("converged", ctypes.c_void_p), ("posterior", ctypes.c_void_p)]
+
+
+PLAN_KINDS = {"single": 0, "tiered": 1, "per_code": 2}
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("tile_frames", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reg_budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        kind = {v: k for k, v in PLAN_KINDS.items()}.get(self.kind, self.kind)
+        return dict(kind=kind, tile_frames=self.tile_frames, waves_per_block=self.waves_per_block,
+                    blocks_per_cu=self.blocks_per_cu, reg_budget=self.reg_budget)
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("plan", Plan), ("ms", ctypes.c_float)]
+
+
+def plan(kind="single", tile_frames=8, waves_per_block=4, blocks_per_cu=0, reg_budget=0) -> Plan:
+    if kind not in PLAN_KINDS:
+        raise ValueError("unknown plan kind %r" % kind)
+    return Plan(PLAN_KINDS[kind], int(tile_frames), int(waves_per_block), int(blocks_per_cu), int(reg_budget), 0)
+
+
 class GraphInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("m", "n", "n_edges", "k", "dc_max", "dv_max", "words_n", "words_m")]
@@ -67,6 +96,13 @@ def lib():
             "sagms_decode": [vp, vp, vp, vp, i64, vp, vp, vp, vp],
             "sagms_decode_soft": [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp],
             "sagms_judge": [vp, vp, vp, vp, vp, i64, vp, vp, vp],
+            "sagms_batch_create": [vp, i32, vp, vp],
+            "sagms_batch_set_plan": [vp, vp],
+            "sagms_batch_get_plan": [vp, vp],
+            "sagms_batch_run": [vp, vp],
+            "sagms_batch_instantiate": [vp],
+            "sagms_batch_tune": [vp, vp, i32, vp, i32, vp, vp],
+            "sagms_batch_destroy": [vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -248,3 +284,69 @@ def frame_buffers(g: Graph, nframes: int, device="cuda", with_ez=True):
         converged=torch.empty((nframes,), dtype=torch.uint8, **z),
         fail=torch.empty((nframes,), dtype=torch.uint8, **z),
     )
+
+
+class Batch:
+    """A mixed-code batch (``sagms_batch_*``).
+
+    ``segments`` is a list of dicts with keys graph, synd, llr0, ehat, iters,
+    converged and optionally posterior (device tensors shaped as for
+    ``decode``).  The tensors are referenced by the batch: they must stay
+    alive, and in place, as long as it does.
+    """
+
+    def __init__(self, segments, cfg: DecoderConfig):
+        import torch
+        n = len(segments)
+        arr = (Segment * max(n, 1))()
+        self._keep = []
+        for i, sg in enumerate(segments):
+            g = sg["graph"]
+            nf = int(sg["synd"].shape[0])
+            arr[i].graph = g._h.value if g is not None else None
+            arr[i].synd = _dev_ptr(sg["synd"], torch.int64, (nf, g.words_m), "synd")
+            arr[i].llr0 = _dev_ptr(sg["llr0"], torch.float32, (g.n,), "llr0")
+            arr[i].nframes = nf
+            arr[i].ehat = _dev_ptr(sg["ehat"], torch.int64, (nf, g.words_n), "ehat")
+            arr[i].iters = _dev_ptr(sg["iters"], torch.int32, (nf,), "iters")
+            arr[i].converged = _dev_ptr(sg["converged"], torch.uint8, (nf,), "converged")
+            arr[i].posterior = _dev_ptr(sg.get("posterior"), torch.float32, (nf, g.n), "posterior")
+            self._keep.append(sg)
+        self._cfg = cfg
+        h = ctypes.c_void_p()
+        _check(lib().sagms_batch_create(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def set_plan(self, p: Plan):
+        _check(lib().sagms_batch_set_plan(self._h, ctypes.byref(p)))
+
+    def get_plan(self) -> Plan:
+        p = Plan()
+        _check(lib().sagms_batch_get_plan(self._h, ctypes.byref(p)))
+        return p
+
+    def run(self, stream=None):
+        _check(lib().sagms_batch_run(self._h, _stream(stream)))
+
+    def instantiate(self):
+        _check(lib().sagms_batch_instantiate(self._h))
+
+    def tune(self, reps=3, stream=None, cap=256):
+        """Runs the autotuner; returns (best plan, [(plan dict, ms), ...])."""
+        res = (TuneResult * cap)()
+        cnt = ctypes.c_int32()
+        best = Plan()
+        _check(lib().sagms_batch_tune(self._h, _stream(stream), int(reps), ctypes.cast(res, ctypes.c_void_p), cap,
+                                      ctypes.byref(cnt), ctypes.byref(best)))
+        return best, [(res[i].plan.as_dict(), float(res[i].ms)) for i in range(cnt.value)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sagms_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

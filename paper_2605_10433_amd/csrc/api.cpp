@@ -7,8 +7,11 @@ using namespace sagms;
 
 namespace {
 
-constexpr int kDecodeFramesPerWave = 8;
 constexpr int kSampleFramesPerWave = 4;
+
+}  // namespace
+
+namespace sagms {
 
 int check_cfg(const sagms_decoder_cfg* c) {
     if (!c) return fail(SAGMS_EINVAL, "cfg is null");
@@ -34,7 +37,43 @@ int check_cfg(const sagms_decoder_cfg* c) {
     return SAGMS_OK;
 }
 
-}  // namespace
+int cfg_gains(Graph* g, DeviceTables* t, const sagms_decoder_cfg* cfg, const float** out, hipStream_t st) {
+    GainKey key{cfg->kind, 0.0, 0.0, 0.0, 0.0};
+    if (cfg->kind == SAGMS_SMS) key.a = cfg->alpha;
+    if (cfg->kind == SAGMS_SAGMS) {
+        key.amin = cfg->alpha_min;
+        key.amax = cfg->alpha_max;
+        key.eta = cfg->eta;
+    }
+    if (cfg->kind == SAGMS_BP) key.kind = SAGMS_MS;  // BP ignores the gains
+    return gain_table(g, t, key, out, st);
+}
+
+DecodeArgs decode_args(const Graph* g, const DeviceTables* t, const float* gains, const uint64_t* synd,
+                       const float* llr0, int64_t nframes, uint64_t* ehat, int32_t* iters, uint8_t* converged,
+                       float* posterior, int lmax, int frames_per_wave) {
+    DecodeArgs a{};
+    a.synd = synd;
+    a.llr0 = llr0;
+    a.gains = gains;
+    a.cn_addr = t->cn_addr;
+    a.vn_addr = t->vn_addr;
+    a.ehat = ehat;
+    a.iters = iters;
+    a.conv = converged;
+    a.post = posterior;
+    a.nframes = nframes;
+    a.m = g->m;
+    a.n = g->n;
+    a.wm = g->wm;
+    a.wn = g->wn;
+    a.lmax = lmax;
+    a.frames_per_wave = frames_per_wave > 0 ? frames_per_wave : kDecodeFramesPerWave;
+    a.L = g->layout;
+    return a;
+}
+
+}  // namespace sagms
 
 extern "C" {
 
@@ -94,35 +133,11 @@ int sagms_decode_soft(sagms_graph gh, const uint64_t* synd, const float* llr0, c
     DeviceTables* t = nullptr;
     rc = device_tables(g, &t, st);
     if (rc) return rc;
-    GainKey key{cfg->kind, 0.0, 0.0, 0.0, 0.0};
-    if (cfg->kind == SAGMS_SMS) key.a = cfg->alpha;
-    if (cfg->kind == SAGMS_SAGMS) {
-        key.amin = cfg->alpha_min;
-        key.amax = cfg->alpha_max;
-        key.eta = cfg->eta;
-    }
-    if (cfg->kind == SAGMS_BP) key.kind = SAGMS_MS;  // BP ignores the gains
     const float* gains = nullptr;
-    rc = gain_table(g, t, key, &gains, st);
+    rc = cfg_gains(g, t, cfg, &gains, st);
     if (rc) return rc;
-    DecodeArgs a{};
-    a.synd = synd;
-    a.llr0 = llr0;
-    a.gains = gains;
-    a.cn_addr = t->cn_addr;
-    a.vn_addr = t->vn_addr;
-    a.ehat = ehat;
-    a.iters = iters;
-    a.conv = converged;
-    a.post = posterior;
-    a.nframes = nframes;
-    a.m = g->m;
-    a.n = g->n;
-    a.wm = g->wm;
-    a.wn = g->wn;
-    a.lmax = cfg->lmax;
-    a.frames_per_wave = cfg->frames_per_wave > 0 ? cfg->frames_per_wave : kDecodeFramesPerWave;
-    a.L = g->layout;
+    const DecodeArgs a = decode_args(g, t, gains, synd, llr0, nframes, ehat, iters, converged, posterior, cfg->lmax,
+                                     cfg->frames_per_wave);
     return launch_decode(g->shape, cfg->kind == SAGMS_BP, cfg->msg_precision, a, st);
 }
 

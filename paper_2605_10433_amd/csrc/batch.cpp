@@ -1,0 +1,389 @@
+// Mixed-code batches: segment table, launch plans, HIP graph capture and the
+// plan autotuner.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "internal.h"
+
+using namespace sagms;
+
+namespace {
+
+constexpr int kDefaultQueues = 8;  // one per XCD: a block starts on queue blockIdx mod 8
+
+struct Batch {
+    int device = 0;
+    sagms_decoder_cfg cfg{};
+    int mt = SAGMS_MSG_FP32;
+    int nseg = 0;
+    int num_cu = 0;
+    // segments in launch order: register tier descending, then cost per frame
+    std::vector<MixedSegment> segs;
+    std::vector<int> tier;     // per segment
+    std::vector<DecodeShape> shape;
+    uint32_t* d_queues = nullptr;  // kNumMixedTiers blocks of kMaxQueues counters
+    sagms_plan plan{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // resident blocks per CU by (tier, register budget, waves per block)
+    std::map<std::tuple<int, int, int>, int> occupancy;
+};
+
+int tier_of_shape(int idx) {
+    for (int t = 0; t < kNumMixedTiers; ++t)
+        if (idx <= kMixedTiers[t]) return t;
+    return -1;
+}
+
+void drop_graph(Batch* b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+int check_plan(const Batch* b, const sagms_plan* p) {
+    if (!p) return fail(SAGMS_EINVAL, "plan is null");
+    if (p->kind < SAGMS_PLAN_SINGLE || p->kind > SAGMS_PLAN_PER_CODE) return fail(SAGMS_EINVAL, "unknown plan kind %d", p->kind);
+    if (p->tile_frames < 1 || p->tile_frames > 1024) return fail(SAGMS_EINVAL, "tile_frames must lie in [1, 1024]");
+    if (p->reserved != 0) return fail(SAGMS_EINVAL, "reserved field must be 0");
+    if (p->kind == SAGMS_PLAN_PER_CODE) return SAGMS_OK;
+    if (p->waves_per_block != 1 && p->waves_per_block != 2 && p->waves_per_block != 4)
+        return fail(SAGMS_EINVAL, "waves_per_block must be 1, 2 or 4");
+    if (p->blocks_per_cu < 0 || p->blocks_per_cu > 64) return fail(SAGMS_EINVAL, "blocks_per_cu must lie in [0, 64]");
+    if (p->reg_budget != 0 && p->reg_budget != 1) return fail(SAGMS_EINVAL, "reg_budget must be 0 or 1");
+    return SAGMS_OK;
+}
+
+// Waves per block of a tier: the plan's, halved until the block's LDS
+// slices fit 64 KiB.
+int waves_of(int tier, int requested) {
+    int w = requested;
+    while (w > 1 && (size_t)w * mixed_words(tier) * sizeof(float) > 65536) w /= 2;
+    return w;
+}
+
+// The tight register budget where the tier has one, else the compiler's.
+int budget_of(int tier, int requested) { return requested == 1 && mixed_has_budget(tier, 1) ? 1 : 0; }
+
+int blocks_per_cu(Batch* b, int tier, int* out) {
+    const int budget = budget_of(tier, b->plan.reg_budget);
+    const int wpb = waves_of(tier, b->plan.waves_per_block);
+    const auto key = std::make_tuple(tier, budget, wpb);
+    auto it = b->occupancy.find(key);
+    if (it == b->occupancy.end()) {
+        int n = 0;
+        int rc = mixed_max_blocks(tier, budget, b->mt, wpb, &n);
+        if (rc) return rc;
+        it = b->occupancy.emplace(key, n).first;
+    }
+    *out = it->second;
+    return SAGMS_OK;
+}
+
+// One persistent launch over segments [s0, s1) with the kernel of `tier`.
+int launch_group(Batch* b, int s0, int s1, int tier, hipStream_t st) {
+    const sagms_plan& p = b->plan;
+    MixedArgs m{};
+    for (int s = s0; s < s1; ++s) m.segs[s - s0] = b->segs[s];
+    m.queues = b->d_queues + (size_t)tier * kMaxQueues * kQueueStride;
+    m.nseg = s1 - s0;
+    m.tile_frames = p.tile_frames;
+    m.words = mixed_words(tier);
+    int64_t tiles = 0;
+    for (int s = s0; s < s1; ++s) {
+        tiles += (b->segs[s].a.nframes + p.tile_frames - 1) / p.tile_frames;
+        m.tile_end[s - s0] = tiles;
+    }
+    if (tiles == 0) return SAGMS_OK;
+    if (tiles > 0x7fffffffLL) return fail(SAGMS_EINVAL, "too many tiles for one launch: raise tile_frames");
+    m.ntiles = tiles;
+    m.nq = (int)std::min<int64_t>(kDefaultQueues, tiles);
+    int per_cu = 0;
+    int rc = blocks_per_cu(b, tier, &per_cu);
+    if (rc) return rc;
+    if (per_cu < 1) return fail(SAGMS_EUNSUPPORTED, "mixed kernel of tier %d does not fit a compute unit", tier);
+    if (p.blocks_per_cu > 0) per_cu = std::min(per_cu, p.blocks_per_cu);
+    const int wpb = waves_of(tier, p.waves_per_block);
+    int64_t blocks = (int64_t)per_cu * b->num_cu;
+    blocks = std::min<int64_t>(blocks, (tiles + wpb - 1) / wpb);
+    return launch_mixed(tier, budget_of(tier, p.reg_budget), b->mt, m, (int)blocks, wpb, st);
+}
+
+int enqueue(Batch* b, hipStream_t st) {
+    const sagms_plan& p = b->plan;
+    if (p.kind == SAGMS_PLAN_PER_CODE) {
+        for (int s = 0; s < b->nseg; ++s) {
+            if (b->segs[s].a.nframes == 0) continue;
+            DecodeArgs a = b->segs[s].a;
+            a.frames_per_wave = p.tile_frames;
+            int rc = launch_decode(b->shape[s], false, b->mt, a, st);
+            if (rc) return rc;
+        }
+        return SAGMS_OK;
+    }
+    if (p.kind == SAGMS_PLAN_SINGLE) return launch_group(b, 0, b->nseg, b->tier.front(), st);
+    for (int s0 = 0; s0 < b->nseg;) {
+        int s1 = s0;
+        while (s1 < b->nseg && b->tier[s1] == b->tier[s0]) ++s1;
+        int rc = launch_group(b, s0, s1, b->tier[s0], st);
+        if (rc) return rc;
+        s0 = s1;
+    }
+    return SAGMS_OK;
+}
+
+int check_device(const Batch* b) {
+    int dev = -1;
+    SAGMS_HIP(hipGetDevice(&dev));
+    if (dev != b->device) return fail(SAGMS_EINVAL, "batch was created on device %d, current device is %d", b->device, dev);
+    return SAGMS_OK;
+}
+
+void destroy(Batch* b) {
+    drop_graph(b);
+    if (b->d_queues) hipFree(b->d_queues);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_decoder_cfg* cfg, sagms_batch* out) {
+    if (!out) return fail(SAGMS_EINVAL, "out is null");
+    *out = nullptr;
+    if (!segs) return fail(SAGMS_EINVAL, "segs is null");
+    if (nseg < 1 || nseg > kMaxSegments) return fail(SAGMS_EINVAL, "nseg must lie in [1, %d]", kMaxSegments);
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (cfg->kind == SAGMS_BP) return fail(SAGMS_EUNSUPPORTED, "batches run MS, SMS and SAGMS only");
+    for (int s = 0; s < nseg; ++s) {
+        const sagms_segment& x = segs[s];
+        Graph* g = reinterpret_cast<Graph*>(x.graph);
+        if (!g) return fail(SAGMS_EINVAL, "segment %d: null graph", s);
+        if (!g->shape_ok) return fail(SAGMS_EUNSUPPORTED, "segment %d: no decode kernel fits the code", s);
+        if (shape_index(g->shape) < 0) return fail(SAGMS_EUNSUPPORTED, "segment %d: shape not compiled", s);
+        if (x.nframes < 0) return fail(SAGMS_EINVAL, "segment %d: nframes must be >= 0", s);
+        if (x.nframes > 0 && (!x.synd || !x.llr0 || !x.ehat || !x.iters || !x.converged))
+            return fail(SAGMS_EINVAL, "segment %d: null buffer", s);
+    }
+    Batch* b = new Batch();
+    b->cfg = *cfg;
+    b->mt = cfg->msg_precision;
+    b->nseg = nseg;
+    b->plan = sagms_plan{SAGMS_PLAN_SINGLE, kDecodeFramesPerWave, 4, 0, 0, 0};
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e != hipSuccess) {
+        destroy(b);
+        return hip_fail(e, "hipGetDevice / hipDeviceGetAttribute");
+    }
+    // launch order: largest register tier first, then the most lane slots per
+    // round (the most expensive frames first), then the caller's order
+    std::vector<int> order(nseg);
+    std::iota(order.begin(), order.end(), 0);
+    auto cost = [&](int s) {
+        const DecodeShape& sh = reinterpret_cast<Graph*>(segs[s].graph)->shape;
+        return sh.cpl * sh.dc + sh.vpl * sh.dv;
+    };
+    auto tier = [&](int s) { return tier_of_shape(shape_index(reinterpret_cast<Graph*>(segs[s].graph)->shape)); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (tier(x) != tier(y)) return tier(x) > tier(y);
+        return cost(x) > cost(y);
+    });
+    for (int s : order) {
+        const sagms_segment& x = segs[s];
+        Graph* g = reinterpret_cast<Graph*>(x.graph);
+        DeviceTables* t = nullptr;
+        const float* gains = nullptr;
+        rc = device_tables(g, &t, nullptr);
+        if (!rc) rc = cfg_gains(g, t, cfg, &gains, nullptr);
+        if (rc) {
+            destroy(b);
+            return rc;
+        }
+        MixedSegment ms{};
+        ms.a = decode_args(g, t, gains, x.synd, x.llr0, x.nframes, x.ehat, x.iters, x.converged, x.posterior,
+                           cfg->lmax, 0);
+        ms.shape = shape_index(g->shape);
+        b->segs.push_back(ms);
+        b->tier.push_back(tier(s));
+        b->shape.push_back(g->shape);
+    }
+    e = hipMalloc(&b->d_queues, sizeof(uint32_t) * kNumMixedTiers * kMaxQueues * kQueueStride);
+    if (e == hipSuccess) e = hipDeviceSynchronize();  // gain tables uploaded on the null stream
+    if (e != hipSuccess) {
+        destroy(b);
+        return hip_fail(e, "batch set-up");
+    }
+    *out = reinterpret_cast<sagms_batch>(b);
+    return SAGMS_OK;
+}
+
+int sagms_batch_set_plan(sagms_batch bh, const sagms_plan* plan) {
+    Batch* b = reinterpret_cast<Batch*>(bh);
+    if (!b) return fail(SAGMS_EINVAL, "null batch");
+    int rc = check_plan(b, plan);
+    if (rc) return rc;
+    drop_graph(b);
+    b->plan = *plan;
+    return SAGMS_OK;
+}
+
+int sagms_batch_get_plan(sagms_batch bh, sagms_plan* plan) {
+    Batch* b = reinterpret_cast<Batch*>(bh);
+    if (!b || !plan) return fail(SAGMS_EINVAL, "null argument");
+    *plan = b->plan;
+    return SAGMS_OK;
+}
+
+int sagms_batch_run(sagms_batch bh, void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bh);
+    if (!b) return fail(SAGMS_EINVAL, "null batch");
+    int rc = check_device(b);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (b->exec) {
+        SAGMS_HIP(hipGraphLaunch(b->exec, st));
+        return SAGMS_OK;
+    }
+    return enqueue(b, st);
+}
+
+int sagms_batch_instantiate(sagms_batch bh) {
+    Batch* b = reinterpret_cast<Batch*>(bh);
+    if (!b) return fail(SAGMS_EINVAL, "null batch");
+    int rc = check_device(b);
+    if (rc) return rc;
+    drop_graph(b);
+    if (b->plan.kind != SAGMS_PLAN_PER_CODE)
+        for (int t : b->tier) {  // occupancy queries stay outside the capture
+            int n = 0;
+            rc = blocks_per_cu(b, t, &n);
+            if (rc) return rc;
+        }
+    hipStream_t cs = nullptr;
+    SAGMS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = enqueue(b, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    hipStreamDestroy(cs);
+    if (rc) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph = graph;
+    b->exec = exec;
+    return SAGMS_OK;
+}
+
+int sagms_batch_tune(sagms_batch bh, void* stream, int32_t reps, sagms_tune_result* results, int32_t cap,
+                     int32_t* count, sagms_plan* best) {
+    Batch* b = reinterpret_cast<Batch*>(bh);
+    if (!b) return fail(SAGMS_EINVAL, "null batch");
+    if (reps < 1 || reps > 100) return fail(SAGMS_EINVAL, "reps must lie in [1, 100]");
+    if (cap < 0 || (cap > 0 && !results)) return fail(SAGMS_EINVAL, "results is null");
+    int rc = check_device(b);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    std::vector<sagms_plan> cands;
+    const int tiles[] = {4, 8, 16, 32};
+    const int multi_tier = std::count(b->tier.begin(), b->tier.end(), b->tier.front()) != b->nseg;
+    bool tight = false;  // a tight budget exists for some tier of the batch
+    for (int t : b->tier) tight = tight || mixed_has_budget(t, 1);
+    for (int kind : {SAGMS_PLAN_SINGLE, SAGMS_PLAN_TIERED}) {
+        if (kind == SAGMS_PLAN_TIERED && !multi_tier) continue;
+        for (int budget : {0, 1}) {
+            if (budget == 1 && (kind == SAGMS_PLAN_SINGLE ? !mixed_has_budget(b->tier.front(), 1) : !tight))
+                continue;
+            for (int wpb : {1, 2, 4})
+                for (int tf : tiles) {
+                    // a waves-per-block value that every launched tier halves is a duplicate
+                    bool dup = true;
+                    for (int t : b->tier)
+                        if ((kind == SAGMS_PLAN_TIERED || t == b->tier.front()) && waves_of(t, wpb) == wpb) dup = false;
+                    if (dup) continue;
+                    sagms_plan p{kind, tf, wpb, 0, budget, 0};
+                    if (check_plan(b, &p) == SAGMS_OK) cands.push_back(p);
+                }
+        }
+    }
+    for (int tf : tiles) cands.push_back(sagms_plan{SAGMS_PLAN_PER_CODE, tf, 4, 0, 0, 0});
+    const sagms_plan saved = b->plan;
+    hipGraphExec_t saved_exec = b->exec;
+    hipGraph_t saved_graph = b->graph;
+    b->exec = nullptr;  // time the eager launches
+    b->graph = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    float best_ms = INFINITY;
+    sagms_plan best_plan = saved;
+    int n = 0;
+    for (const sagms_plan& p : cands) {
+        if (he != hipSuccess || rc) break;
+        b->plan = p;
+        rc = enqueue(b, st);  // warm-up
+        std::vector<float> ms;
+        for (int r = 0; r < reps && !rc && he == hipSuccess; ++r) {
+            he = hipEventRecord(e0, st);
+            if (he == hipSuccess) rc = enqueue(b, st);
+            if (he == hipSuccess && !rc) he = hipEventRecord(e1, st);
+            if (he == hipSuccess && !rc) he = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (he == hipSuccess && !rc) he = hipEventElapsedTime(&t, e0, e1);
+            ms.push_back(t);
+        }
+        if (he != hipSuccess || rc) break;
+        std::sort(ms.begin(), ms.end());
+        const float med = ms[ms.size() / 2];
+        if (n < cap) results[n] = sagms_tune_result{p, med};
+        ++n;
+        if (med < best_ms) {
+            best_ms = med;
+            best_plan = p;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (he == hipSuccess && !rc) he = hipStreamSynchronize(st);
+    if (he != hipSuccess || rc) {
+        b->plan = saved;
+        b->exec = saved_exec;
+        b->graph = saved_graph;
+        return rc ? rc : hip_fail(he, "autotuner timing");
+    }
+    b->exec = saved_exec;
+    b->graph = saved_graph;
+    if (best_plan.kind != saved.kind || best_plan.tile_frames != saved.tile_frames ||
+        best_plan.waves_per_block != saved.waves_per_block || best_plan.blocks_per_cu != saved.blocks_per_cu ||
+        best_plan.reg_budget != saved.reg_budget)
+        drop_graph(b);
+    b->plan = best_plan;
+    if (count) *count = std::min(n, cap);
+    if (best) *best = best_plan;
+    return SAGMS_OK;
+}
+
+int sagms_batch_destroy(sagms_batch bh) {
+    Batch* b = reinterpret_cast<Batch*>(bh);
+    if (!b) return fail(SAGMS_EINVAL, "null batch");
+    destroy(b);
+    return SAGMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+#pragma once
+// Device code shared by the decode kernels: MS / SMS / SAGMS (one code path,
+// gain table) and BP.
+//
+// Algorithm 1 of the paper on the binary Tanner graph of H, flooding
+// schedule, one wavefront per frame:
+//   lane l owns checks c = l + 64 k (k < CPL) and variables j = l + 64 k
+//   (k < VPL).  A check keeps its DC outgoing c2v messages in VGPRs; the
+//   posteriors of all variables and the c2v messages of the current round
+//   live in the wave's LDS slice.  One round:
+//     top    every check reads the posteriors of its variables from LDS:
+//            v2c = posterior - own c2v (eq. (bp4_vn) as "total minus own"),
+//            and the XOR of their signs gives (H e_hat)_c; the residual
+//            syndrome s_res = s xor H e_hat is balloted, its popcount w is
+//            the unsatisfied-check count of eq. (synratio).  w == 0 ends
+//            the frame (converged), as does reaching lmax rounds.
+//     CN     eq. (ms_cn) with min1 / min2 / sign parity over the row, the
+//            sign of (-1)^{s_c} folded into the parity; the output
+//            magnitude is gain * (|v2c| == min1 ? min2 : min1), the gain
+//            taken from a table indexed by w and by the check's residual
+//            bit (eq. (alphaeff); 1 for MS, alpha for SMS).  BP replaces
+//            this by eq. (bp4_cn) in tanh form, evaluated in FP64.
+//     VN     every variable sums L0 and its incoming c2v messages in the
+//            graph's order (ascending check index, or polynomial-term order
+//            for a GB code) and stores the posterior (eq. (bp4_vn)).
+//   The hard decision is e_hat_j = [posterior_j < 0].
+// Posteriors and v2c messages are never -0.0 (L0 is read as L0 + 0.0f and
+// every later value is a sum or a difference of finite floats starting from
+// it), so sign bits and "< 0" agree and the kernel uses sign bits.
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+
+namespace sagms {
+
+constexpr uint32_t kSign = 0x80000000u;
+
+// LDS traffic of one wave only: the LDS unit executes a wave's requests in
+// order, so a wavefront-scope fence (compiler ordering) is all that is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// FP64 exclusive-product BP check update (eq. (bp4_cn) in tanh form):
+// out_p = 2 atanh(prod_{q != p} tanh(|v_q| / 2)), product capped at
+// 1 - 2^-40 so that the output stays finite.
+template <int DC>
+__device__ __forceinline__ void bp_magnitudes(const float (&v)[DC], float (&out)[DC]) {
+    double t[DC], pre[DC];
+    double acc = 1.0;
+#pragma unroll
+    for (int p = 0; p < DC; ++p) {
+        t[p] = tanh(0.5 * (double)fabsf(v[p]));
+        pre[p] = acc;
+        acc *= t[p];
+    }
+    double suf = 1.0;
+    const double cap = 1.0 - 0x1.0p-40;
+#pragma unroll
+    for (int p = DC - 1; p >= 0; --p) {
+        double x = fmin(pre[p] * suf, cap);
+        out[p] = (float)(2.0 * atanh(x));
+        suf *= t[p];
+    }
+}
+
+// Compile-time LDS layout of one wave (32-bit words); must equal make_layout().
+template <int DC, int CPL, int VPL>
+struct Lay {
+    static constexpr int CW = 64 * CPL;
+    static constexpr int ZERO = DC * CW;
+    static constexpr int POST0 = ZERO + 1;
+    static constexpr int PADPOST = POST0 + 64 * VPL;
+    static constexpr int GAIN0 = (PADPOST + 2) & ~1;
+    static constexpr int WORDS = GAIN0 + 2 * (CW + 1);
+};
+
+__device__ __forceinline__ uint32_t bits(float x) { return __float_as_uint(x); }
+
+// gfx950 3-input bit operations (truth table indexed by a*4 + b*2 + c):
+// a ^ b ^ c (0x96) and a ^ (b & c) (0x78).  The compiler re-associates XOR
+// chains into 2-input steps unless asked for the 3-input form.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x78);
+}
+
+// Sign bit of init XOR the signs of x[0..N-1], two inputs per step.
+template <int N>
+__device__ __forceinline__ uint32_t xor_signs(const float (&x)[N], uint32_t init) {
+    uint32_t acc = init;
+#pragma unroll
+    for (int p = 0; p + 1 < N; p += 2) acc = xor3(acc, bits(x[p]), bits(x[p + 1]));
+    if constexpr (N % 2) acc ^= bits(x[N - 1]);
+    return acc & kSign;
+}
+
+// Message formats: FP32; FP16 (every message saturated to +-65504 and
+// rounded to half, posteriors FP32); INT6 (sign + 6-bit magnitude on a grid
+// of step 1/4, saturating at +-63 steps; the prior is quantized as well, so
+// posterior sums are exact).  Messages are held as FP32 values on the grid.
+template <int MT>
+__device__ __forceinline__ float quantize(float x) {
+    if constexpr (MT == SAGMS_MSG_FP16) {
+        return __half2float(__float2half_rn(__builtin_amdgcn_fmed3f(x, -65504.0f, 65504.0f)));
+    } else if constexpr (MT == SAGMS_MSG_INT6) {
+        return __builtin_amdgcn_fmed3f(rintf(x * 4.0f), -63.0f, 63.0f) * 0.25f;
+    } else {
+        return x;
+    }
+}
+
+// Check-node update of one check (eq. (ms_cn) scaled per eq. (alphaeff) /
+// (sagms_cn), or eq. (bp4_cn) for BP): v = incoming v2c messages, sb = the
+// original syndrome bit, res = the residual bit (both at the sign position),
+// gs / gu = the gains of a satisfied / unsatisfied check.
+template <int DC, bool BP, int MT>
+__device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, uint32_t res, float gs, float gu,
+                                          float (&c2v)[DC]) {
+    const uint32_t par = xor_signs<DC>(v, sb);
+    if constexpr (BP) {
+        float mag[DC];
+        bp_magnitudes<DC>(v, mag);
+#pragma unroll
+        for (int p = 0; p < DC; ++p) c2v[p] = __uint_as_float(bits(mag[p]) | ((bits(v[p]) ^ par) & kSign));
+    } else {
+        const float alpha = res ? gu : gs;
+        float m1 = __builtin_inff(), m2 = __builtin_inff();
+#pragma unroll
+        for (int p = 0; p < DC; ++p) {
+            float x = fabsf(v[p]);
+            m2 = __builtin_amdgcn_fmed3f(m1, x, m2);
+            m1 = fminf(m1, x);
+        }
+        // two products per check, both magnitudes pre-signed with the check
+        // parity; per edge: compare, select, and one 3-input bit operation
+        // applying the edge's own sign.  The empty asm keeps the compiler
+        // from folding the select back into one product per edge.
+        uint32_t S1 = bits(quantize<MT>(alpha * m1)) | par, S2 = bits(quantize<MT>(alpha * m2)) | par;
+        asm("" : "+v"(S1), "+v"(S2));
+#pragma unroll
+        for (int p = 0; p < DC; ++p) {
+            const uint32_t sel = fabsf(v[p]) == m1 ? S2 : S1;
+            c2v[p] = __uint_as_float(xor_and(sel, bits(v[p]), kSign));
+        }
+    }
+}
+
+// One wave's decoder for one code: graph tables, priors and gains held in
+// registers, loaded once (load) and reused for every frame (frame).  The LDS
+// slice `lds` belongs to this wave alone.
+template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
+struct WaveDecoder {
+    using LY = Lay<DC, CPL, VPL>;
+    uint32_t caddr[CPL][DC];
+    uint32_t vaddr[VPL][DV];
+    float L0[VPL];
+    float gsl, gul, gs64, gu64;
+
+    __device__ __forceinline__ void load(const DecodeArgs& a, float* lds, int lane) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+#pragma unroll
+            for (int p = 0; p < DC; ++p) caddr[k][p] = a.cn_addr[(k * DC + p) * 64 + lane];
+#pragma unroll
+        for (int k = 0; k < VPL; ++k)
+#pragma unroll
+            for (int r = 0; r < DV; ++r) vaddr[k][r] = a.vn_addr[(k * DV + r) * 64 + lane];
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) {
+            int j = k * 64 + lane;
+            L0[k] = j < a.n ? quantize<MT == SAGMS_MSG_INT6 ? MT : SAGMS_MSG_FP32>(a.llr0[j] + 0.0f) : __builtin_inff();
+        }
+        // gain table: in registers (lane w holds entry w) when m <= 64, else in LDS
+        gsl = a.gains[2 * lane];
+        gul = a.gains[2 * lane + 1];
+        gs64 = a.gains[128];
+        gu64 = a.gains[129];
+        if constexpr (CPL > 1)
+            for (int t = lane; t < 2 * (LY::CW + 1); t += 64) lds[LY::GAIN0 + t] = a.gains[t];
+        if (lane == 0) {
+            lds[LY::ZERO] = 0.0f;
+            lds[LY::PADPOST] = __builtin_inff();
+        }
+    }
+
+    // Decodes frame f and writes its outputs.
+    __device__ __forceinline__ void frame(const DecodeArgs& a, float* lds, int lane, int64_t f) {
+        // original syndrome bit of each owned check, at the sign position
+        // (checks beyond m read as 0; their rows hold only the +inf padding)
+        uint32_t sb[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            uint64_t word = k < a.wm ? a.synd[f * a.wm + k] : 0ull;
+            sb[k] = (k * 64 + lane < a.m) ? (uint32_t)((word >> lane) & 1ull) << 31 : 0u;
+        }
+        float post[VPL];
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) {
+            post[k] = L0[k];
+            lds[LY::POST0 + k * 64 + lane] = L0[k];
+        }
+        float c2v[CPL][DC];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+#pragma unroll
+            for (int p = 0; p < DC; ++p) c2v[k][p] = 0.0f;
+        wave_lds_sync();
+
+        int it = 0;
+        bool conv = false;
+        while (true) {
+            // top of the round: v2c, hard-decision parity, residual syndrome
+            float v[CPL][DC];
+            uint32_t res[CPL];  // residual syndrome bit at the sign position
+            int w = 0;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                float pj[DC];
+#pragma unroll
+                for (int p = 0; p < DC; ++p) {
+                    pj[p] = lds[caddr[k][p]];
+                    v[k][p] = quantize<MT>(pj[p] - c2v[k][p]);
+                }
+                res[k] = xor_signs<DC>(pj, sb[k]);
+                w += __builtin_popcountll(ballot(res[k] != 0));
+            }
+            if (w == 0) {
+                conv = true;
+                break;
+            }
+            if (it == a.lmax) break;
+            ++it;
+            // CN update; gains of the residual weight w (eq. (alphaeff))
+            float gs, gu;
+            if constexpr (CPL == 1) {
+                gs = w < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gsl), w)) : gs64;
+                gu = w < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gul), w)) : gu64;
+            } else {
+                const float2 gg = *reinterpret_cast<const float2*>(&lds[LY::GAIN0 + 2 * w]);
+                gs = gg.x;
+                gu = gg.y;
+            }
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                cn_update<DC, BP, MT>(v[k], sb[k], res[k], gs, gu, c2v[k]);
+#pragma unroll
+                for (int p = 0; p < DC; ++p) lds[p * LY::CW + k * 64 + lane] = c2v[k][p];
+            }
+            wave_lds_sync();
+            // VN update: posterior in the graph's summation order
+#pragma unroll
+            for (int k = 0; k < VPL; ++k) {
+                float s = L0[k];
+#pragma unroll
+                for (int r = 0; r < DV; ++r) s = s + lds[vaddr[k][r]];
+                post[k] = s;
+                lds[LY::POST0 + k * 64 + lane] = s;
+            }
+            wave_lds_sync();
+        }
+
+        // outputs: hard decisions, round count, convergence flag
+        uint64_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) {
+            int j = k * 64 + lane;
+            uint64_t word = ballot(j < a.n && post[k] < 0.0f);
+            if (lane == k) mine = word;
+        }
+        if (lane < a.wn) a.ehat[f * a.wn + lane] = mine;
+        if (a.post) {
+#pragma unroll
+            for (int k = 0; k < VPL; ++k) {
+                int j = k * 64 + lane;
+                if (j < a.n) a.post[f * a.n + j] = post[k];
+            }
+        }
+        if (lane == 0) {
+            a.iters[f] = it;
+            a.conv[f] = conv ? 1 : 0;
+        }
+    }
+};
+
+}  // namespace sagms

@@ -77,9 +77,18 @@ static std::vector<uint64_t> gf2_kernel(std::vector<uint64_t> a, int nrows, int 
 
 // ---- decode shapes and LDS layout ----------------------------------------
 static const DecodeShape kShapes[] = {
-    {4, 2, 1, 1},  {6, 3, 1, 1},  {10, 5, 1, 2}, {16, 8, 1, 2}, {10, 5, 2, 4},
-    {16, 8, 2, 4}, {6, 3, 4, 8},  {8, 4, 4, 8},  {10, 5, 8, 16},
+#define SAGMS_SHAPE_ENTRY(I, DC, DV, CPL, VPL) {DC, DV, CPL, VPL},
+    SAGMS_DECODE_SHAPES(SAGMS_SHAPE_ENTRY)
+#undef SAGMS_SHAPE_ENTRY
 };
+static_assert(sizeof(kShapes) / sizeof(kShapes[0]) == kNumShapes, "shape list");
+
+int shape_index(const DecodeShape& s) {
+    for (int i = 0; i < kNumShapes; ++i)
+        if (kShapes[i].dc == s.dc && kShapes[i].dv == s.dv && kShapes[i].cpl == s.cpl && kShapes[i].vpl == s.vpl)
+            return i;
+    return -1;
+}
 
 bool pick_shape(int m, int n, int dc, int dv, DecodeShape* out) {
     bool found = false;

@@ -34,6 +34,27 @@ struct DecodeShape {
     int dc, dv, cpl, vpl;
 };
 
+// Every compiled shape, X(index, DC, DV, CPL, VPL), in increasing order of
+// register use: a mixed-code kernel compiled for shapes 0..HI holds the
+// registers of shape HI (see kMixedTiers).
+#define SAGMS_DECODE_SHAPES(X) \
+    X(0, 4, 2, 1, 1)           \
+    X(1, 6, 3, 1, 1)           \
+    X(2, 10, 5, 1, 2)          \
+    X(3, 16, 8, 1, 2)          \
+    X(4, 10, 5, 2, 4)          \
+    X(5, 6, 3, 4, 8)           \
+    X(6, 16, 8, 2, 4)          \
+    X(7, 8, 4, 4, 8)           \
+    X(8, 10, 5, 8, 16)
+constexpr int kNumShapes = 9;
+// Highest shape index of each mixed-kernel tier: the tiers share one
+// occupancy class each (shapes 0-2 fit 64 VGPRs, 3-4 fit 128, 5-7 fit 168).
+constexpr int kMixedTiers[] = {2, 4, 7, 8};
+constexpr int kNumMixedTiers = 4;
+// Index of a shape in SAGMS_DECODE_SHAPES, or -1.
+int shape_index(const DecodeShape& s);
+
 // Per-wave LDS layout of the decode kernels, in 32-bit words:
 //   c2v slots  [dc][cw]   slot(c, p) = p * cw + c  (cw = 64 * cpl)
 //   zero       one word holding 0.0f (padding of short variables)
@@ -114,6 +135,55 @@ struct DecodeArgs {
     DecodeLayout L;
 };
 int launch_decode(const DecodeShape& s, bool bp, int msg_precision, const DecodeArgs& a, hipStream_t st);
+
+constexpr int kDecodeFramesPerWave = 8;
+// Decoder configuration checks (api.cpp); SAGMS_OK or a status.
+int check_cfg(const sagms_decoder_cfg* c);
+// Device gain table of a configuration on the current device.
+int cfg_gains(Graph* g, DeviceTables* t, const sagms_decoder_cfg* cfg, const float** out, hipStream_t st);
+// Kernel arguments of one decode call (frames_per_wave 0 = default).
+DecodeArgs decode_args(const Graph* g, const DeviceTables* t, const float* gains, const uint64_t* synd,
+                       const float* llr0, int64_t nframes, uint64_t* ehat, int32_t* iters, uint8_t* converged,
+                       float* posterior, int lmax, int frames_per_wave);
+
+// ---- mixed-code persistent decode ---------------------------------------
+// A batch holds up to kMaxSegments segments, each a run of frames of one
+// code.  The frames are cut into tiles of tile_frames frames; the tiles of
+// all segments, in segment order, are dealt round-robin to nq queues (tile t
+// to queue t mod nq, as its (t div nq)-th entry).  A wave starts on queue
+// blockIdx mod nq, takes tiles from it with one atomic increment each, and
+// moves on to the next queue when it is empty; it exits after finding every
+// queue empty once.
+constexpr int kMaxSegments = 16;
+constexpr int kMaxQueues = 16;
+constexpr int kQueueStride = 64;  // 32-bit words between counters (256 B)
+
+struct MixedSegment {
+    DecodeArgs a;
+    int32_t shape;  // index in SAGMS_DECODE_SHAPES
+    int32_t pad;
+};
+
+// Passed by value (kernel arguments, about 2.4 KB): the segment table is
+// read with scalar loads and is captured with the launch in a HIP graph.
+struct MixedArgs {
+    MixedSegment segs[kMaxSegments];
+    uint32_t* queues;                   // device [nq * kQueueStride], zero at launch
+    int64_t tile_end[kMaxSegments];     // tiles of segments 0..s
+    int64_t ntiles;
+    int nseg, nq, tile_frames, words;   // words: LDS words per wave
+};
+
+// LDS words per wave of the mixed kernel of a tier (largest layout in it).
+int mixed_words(int tier);
+// Whether a tier has a kernel with register budget `budget` (0 = the
+// compiler's allocation, 1 = one more resident wave per SIMD).
+bool mixed_has_budget(int tier, int budget);
+// Resident blocks per CU of a mixed kernel (occupancy of registers and LDS).
+int mixed_max_blocks(int tier, int budget, int mt, int waves_per_block, int* out);
+// Zeroes the queue counters, then launches the persistent kernel (MS / SMS /
+// SAGMS; BP has no mixed kernel).
+int launch_mixed(int tier, int budget, int mt, const MixedArgs& m, int blocks, int waves_per_block, hipStream_t st);
 
 
 struct SampleArgs {

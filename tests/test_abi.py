@@ -142,3 +142,45 @@ def test_gen_errors_and_judge_argument_checks():
 def test_prior_llr_matches_oracle(p):
     assert sagms.prior_llr(p) == np.float32(channel.prior_llr(p))
     assert np.isnan(sagms.prior_llr(0.0)) and np.isnan(sagms.prior_llr(0.8))
+
+
+def _segments(graphs, nframes, null_buffers=False):
+    arr = (sagms.Segment * len(graphs))()
+    for i, (g, nf) in enumerate(zip(graphs, nframes)):
+        arr[i].graph = g._h.value if g is not None else None
+        arr[i].nframes = nf
+        if not null_buffers:  # host addresses: the checks read no memory
+            for f in ("synd", "llr0", "ehat", "iters", "converged"):
+                setattr(arr[i], f, 0x1000)
+    return arr
+
+
+def _create_rc(arr, n, cfg):
+    h = ctypes.c_void_p()
+    return sagms.lib().sagms_batch_create(ctypes.cast(arr, ctypes.c_void_p) if arr is not None else None, n,
+                                          ctypes.byref(cfg), ctypes.byref(h))
+
+
+def test_batch_create_checks_before_device_work():
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    cfg = sagms.decoder_config("sagms")
+    assert _create_rc(None, 1, cfg) == sagms.EINVAL
+    assert _create_rc(_segments([g], [4]), 0, cfg) == sagms.EINVAL
+    assert _create_rc(_segments([g] * 17, [4] * 17), 17, cfg) == sagms.EINVAL          # more than 16 segments
+    assert _create_rc(_segments([g, None], [4, 4]), 2, cfg) == sagms.EINVAL            # null graph
+    assert _create_rc(_segments([g], [-1]), 1, cfg) == sagms.EINVAL                    # negative frame count
+    assert _create_rc(_segments([g], [4], null_buffers=True), 1, cfg) == sagms.EINVAL  # null buffers
+    assert _create_rc(_segments([g], [4]), 1, sagms.decoder_config("bp")) == sagms.EUNSUPPORTED
+    assert _create_rc(_segments([g], [4]), 1, sagms.decoder_config("sagms", eta=0.5)) == sagms.EINVAL
+    for name in ("sagms_batch_run", "sagms_batch_instantiate", "sagms_batch_destroy"):
+        assert getattr(sagms.lib(), name)(None, *([None] if name == "sagms_batch_run" else [])) == sagms.EINVAL
+    assert sagms.lib().sagms_batch_set_plan(None, ctypes.byref(sagms.plan())) == sagms.EINVAL
+    assert sagms.lib().sagms_batch_tune(None, None, 1, None, 0, None, None) == sagms.EINVAL
+
+
+def test_plan_structures():
+    p = sagms.plan("tiered", tile_frames=16, waves_per_block=2, blocks_per_cu=3, reg_budget=1)
+    assert p.as_dict() == dict(kind="tiered", tile_frames=16, waves_per_block=2, blocks_per_cu=3, reg_budget=1)
+    assert ctypes.sizeof(sagms.Plan) == 24 and ctypes.sizeof(sagms.Segment) == 64
+    with pytest.raises(ValueError):
+        sagms.plan("bogus")

@@ -29,6 +29,25 @@ SAGMS_PARAMS = dict(alpha_min=0.30, alpha_max=0.50, eta=1.10)   # Section V setu
 CALIB = dict(code="G63", p=0.05, seed=1, stream=0, frames=10_000, lmax=50)
 
 
+# The mixed-code workload: 2^22 frames split 40 / 30 / 20 / 10 % over four GB
+# codes of different length and degree (each share rounded to the nearest
+# frame; the four sum to exactly 2^22), p = 0.04, l_max = 100.
+MIX_CODES = ["G127", "G255w3", "G255w4", "G63"]
+MIX_SHARES = [0.4, 0.3, 0.2, 0.1]
+MIX_TOTAL = 1 << 22
+MIX_FRAMES = [int(round(f * MIX_TOTAL)) for f in MIX_SHARES]
+MIX_P = 0.04
+MIX_LMAX = 100
+MIX_SEED = 3
+# The reduced-precision study runs the same mix at these noise levels.
+PRECISION_P = [0.03, 0.05]
+
+
+def mix_stream(i: int, p: float) -> int:
+    """Philox stream of mix segment i at noise level p (distinct per pair)."""
+    return 100 + 10 * i + int(round(p * 100))
+
+
 def stream_of(p: float) -> int:
     """Philox stream of a sweep point: the index of p in the grid."""
     return P_GRID.index(p)
