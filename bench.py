@@ -209,6 +209,125 @@ def run_mix(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args):
+    """The serving workload: the five-code batch throughput first (one tuned
+    sagms_batch_run over equal shares of 2^20 frames), then open-loop Poisson
+    traces at the offered loads, replayed in real time by the server; one
+    JSON line per load with p50 / p99 latency and served throughput."""
+    import torch
+
+    import paper_2605_10433_amd as sagms
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = workloads.SERVE_P
+    cfg = sagms.decoder_config(args.decoder, lmax=workloads.SERVE_LMAX, alpha=args.alpha, precision=args.precision,
+                               **workloads.SAGMS_PARAMS)
+    graphs = [sagms.Graph.gb(*workloads.code(n)) for n in workloads.SERVE_CODES]
+
+    # batch throughput of the same code mix (equal frame shares)
+    share = (1 << 20) // len(graphs)
+    segs = []
+    for i, g in enumerate(graphs):
+        buf = sagms.frame_buffers(g, share, device=dev, with_ez=False)
+        sagms.gen_errors(g, workloads.SERVE_SEED, workloads.serve_stream(i), 1 << 30, share, p, buf["ex"], None,
+                         buf["synd"])
+        segs.append(dict(graph=g, synd=buf["synd"], ehat=buf["ehat"], iters=buf["iters"], converged=buf["converged"],
+                         llr0=torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)))
+    batch = sagms.Batch(segs, cfg)
+    best, _ = batch.tune(reps=2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(3):
+        e0.record()
+        batch.run()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    batch_ms = float(np.median(times))
+    batch_fps = share * len(graphs) / (batch_ms * 1e-3)
+    batch.close()
+    del segs
+
+    srv = sagms.Server(graphs, [np.full(g.n, sagms.prior_llr(p), dtype=np.float32) for g in graphs], cfg,
+                       sagms.server_config(max_frames_in_flight=args.serve_launch_frames * args.serve_streams,
+                                           max_frames_per_launch=args.serve_launch_frames, streams=args.serve_streams,
+                                           tile_frames=args.serve_tile, waves_per_block=4, reg_budget=1))
+    mean_frames = (workloads.SERVE_MAX_FRAMES + 1) / 2.0
+    for li, load in enumerate(workloads.SERVE_LOADS):
+        rate = load * batch_fps / mean_frames
+        nreq = int(rate * args.serve_seconds)
+        code, size, arrive = workloads.serve_trace(rate, nreq)
+        reqs = np.zeros(nreq, dtype=sagms.REQUEST_DTYPE)
+        keep = []
+        for c, g in enumerate(graphs):
+            sel = np.nonzero(code == c)[0]
+            total = int(size[sel].sum())
+            synd = np.empty((max(total, 1), g.words_m), dtype=np.uint64)
+            chunk = 1 << 20
+            for f0 in range(0, total, chunk):
+                nf = min(chunk, total - f0)
+                buf = sagms.frame_buffers(g, nf, device=dev, with_ez=False)
+                sagms.gen_errors(g, workloads.SERVE_SEED, workloads.serve_stream(c), (li << 28) + f0, nf, p,
+                                 buf["ex"], None, buf["synd"])
+                synd[f0:f0 + nf] = buf["synd"].cpu().numpy().view(np.uint64)
+            ehat = np.zeros((max(total, 1), g.words_n), dtype=np.uint64)
+            iters = np.zeros(max(total, 1), dtype=np.int32)
+            conv = np.zeros(max(total, 1), dtype=np.uint8)
+            keep += [synd, ehat, iters, conv]
+            lo = np.concatenate([[0], np.cumsum(size[sel])[:-1]]).astype(np.int64) if len(sel) else np.zeros(0, np.int64)
+            reqs["code"][sel] = c
+            reqs["nframes"][sel] = size[sel]
+            reqs["synd"][sel] = synd.ctypes.data + lo * g.words_m * 8
+            reqs["ehat"][sel] = ehat.ctypes.data + lo * g.words_n * 8
+            reqs["iters"][sel] = iters.ctypes.data + lo * 4
+            reqs["converged"][sel] = conv.ctypes.data + lo
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        done = srv.replay(reqs, arrive, timeout_s=60.0)
+        wall = time.perf_counter() - w0
+        lat = done["done_us"] - done["submit_us"]
+        frames = int(size.sum())
+        span_s = (done["done_us"].max() - done["submit_us"].min()) * 1e-6
+        out = {
+            "metric": "mixed-code p50/p99 latency",
+            "value": float(np.percentile(lat, 99)),
+            "unit": "us (p99)",
+            "higher_is_better": False,
+            "n_gpus": 1,
+            "dtype": {"fp32": "f32", "fp16": "f16 messages, f32 posteriors", "int6": "int6 messages"}[args.precision],
+            "data": "synthetic",
+            "p50_us": float(np.percentile(lat, 50)),
+            "p99_us": float(np.percentile(lat, 99)),
+            "mean_us": float(lat.mean()),
+            "wait_p50_us": float(np.percentile(done["admit_us"] - done["submit_us"], 50)),
+            "wait_p99_us": float(np.percentile(done["admit_us"] - done["submit_us"], 99)),
+            "service_p50_us": float(np.percentile(done["done_us"] - done["admit_us"], 50)),
+            "service_p99_us": float(np.percentile(done["done_us"] - done["admit_us"], 99)),
+            "per_code_p50_p99_us": {n: [float(np.percentile(lat[code == c], 50)), float(np.percentile(lat[code == c], 99))]
+                                    for c, n in enumerate(workloads.SERVE_CODES)},
+            "offered_load": load,
+            "offered_frames_per_s": rate * mean_frames,
+            "served_frames_per_s": frames / span_s,
+            "batch_frames_per_s": batch_fps,
+            "batch_ms_2pow20": batch_ms,
+            "batch_plan": best.as_dict(),
+            "requests": nreq,
+            "frames": frames,
+            "wall_s": wall,
+            "config": {"workload": "serving: Poisson arrivals (seed %d), requests of U{1..%d} syndromes of one of %s "
+                                   "chosen uniformly, p=%g, %s l_max=%d, %s messages"
+                                   % (workloads.SERVE_SEED, workloads.SERVE_MAX_FRAMES, "/".join(workloads.SERVE_CODES),
+                                      p, args.decoder.upper(), workloads.SERVE_LMAX, args.precision.upper()),
+                       "max_frames_per_launch": args.serve_launch_frames, "streams": args.serve_streams,
+                       "tile_frames": args.serve_tile},
+        }
+        print(json.dumps(out), flush=True)
+        del keep
+    srv.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,9 +335,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1 << 20)
     ap.add_argument("--p", type=float, default=None, help="noise level (default 0.05; 0.04 for the mix)")
-    ap.add_argument("--workload", default="g63", choices=["g63", "mix"],
+    ap.add_argument("--workload", default="g63", choices=["g63", "mix", "serve"],
                     help="g63: the l = 63 code, 2^20 frames per step; mix: four GB codes, 2^22 frames per step "
-                         "in one batch")
+                         "in one batch; serve: Poisson request traces over five codes through the server")
+    ap.add_argument("--serve-seconds", type=float, default=0.25, help="serve: length of each arrival trace")
+    ap.add_argument("--serve-launch-frames", type=int, default=1 << 15, help="serve: max frames per launch")
+    ap.add_argument("--serve-streams", type=int, default=4, help="serve: launches in flight")
+    ap.add_argument("--serve-tile", type=int, default=8, help="serve: frames per queue tile")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "int6"], help="message format (mix)")
     ap.add_argument("--plan", default="", help="mix: launch plan as JSON, e.g. '{\"kind\": \"tiered\"}'")
     ap.add_argument("--tune", action="store_true", help="mix: run the plan autotuner before timing")
@@ -244,6 +367,9 @@ def main():
 
     if args.workload == "mix":
         run_mix(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
     if args.p is None:
         args.p = 0.05

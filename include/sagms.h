@@ -290,6 +290,86 @@ int sagms_batch_tune(sagms_batch b, void* stream, int32_t reps, sagms_tune_resul
 
 int sagms_batch_destroy(sagms_batch b);
 
+/* ---- serving ----------------------------------------------------------
+ * Continuous batching of decode requests (Algorithm 1 on each request's
+ * frames, one decoder configuration, several codes).  Requests wait in one
+ * FIFO per register class of the codes.  Each progress step first retires
+ * finished launches (their outputs are copied to the requests' host buffers
+ * and their completions recorded), then, while one of the server's streams
+ * is free, takes the class whose oldest waiting request is oldest and admits
+ * requests from it in order while the launch holds at most
+ * max_frames_per_launch frames and all launches in flight at most
+ * max_frames_in_flight frames (the device-memory budget); the admitted
+ * frames go to the GPU as one copy, one persistent mixed-code launch and one
+ * copy back, on that stream.  Launches on different streams overlap on the
+ * device, so requests that arrive while others run are admitted as soon as a
+ * stream and budget are free.  Every frame's outputs equal those of
+ * sagms_decode on that frame alone.  A server is used from one host thread. */
+
+typedef struct sagms_server_s* sagms_server;
+
+typedef struct {
+    int64_t max_frames_in_flight;  /* frames in all launches in flight, >= max_frames_per_launch */
+    int32_t max_frames_per_launch; /* 1 .. 2^24; also the largest request    */
+    int32_t streams;               /* launches in flight at once, 1 .. 8     */
+    int32_t tile_frames;           /* persistent-kernel tile, 1 .. 1024      */
+    int32_t waves_per_block;       /* 1, 2 or 4 (halved where LDS needs it)  */
+    int32_t reg_budget;            /* 0 or 1, as in sagms_plan               */
+    int32_t reserved;              /* must be 0                              */
+} sagms_server_cfg;
+
+typedef struct {
+    int32_t code;                /* index of the graph given at creation          */
+    int32_t nframes;             /* 1 .. max_frames_per_launch                    */
+    const uint64_t* synd;        /* host [nframes][words_m]; read at admission    */
+    uint64_t* ehat;              /* host [nframes][words_n]                       */
+    int32_t* iters;              /* host [nframes]                                */
+    uint8_t* converged;          /* host [nframes]                                */
+    double deadline_us;          /* cancel if not admitted within this many us
+                                    after submission; 0 = no deadline             */
+} sagms_request;
+
+enum { SAGMS_REQ_DONE = 0, SAGMS_REQ_CANCELLED = 1 };
+
+typedef struct {
+    int64_t id;                  /* as returned by sagms_server_submit            */
+    int32_t status;              /* SAGMS_REQ_DONE or SAGMS_REQ_CANCELLED         */
+    int32_t reserved;
+    double submit_us;            /* server clock (us since creation)              */
+    double admit_us;             /* when its launch was enqueued (-1: cancelled)  */
+    double done_us;              /* when the host saw its launch finish           */
+} sagms_completion;
+
+/* Creates a server for ncodes (1..16) graphs with host prior vectors
+ * llr0_host[c] (float [n_c], copied), decoder cfg (MS, SMS or SAGMS) and
+ * serving configuration scfg, on the current device.  Allocates its streams,
+ * pinned staging and device buffers (in all: streams x max_frames_per_launch
+ * frames of syndromes and outputs) and synchronizes the device. */
+int sagms_server_create(const sagms_graph* graphs, const float* const* llr0_host, int32_t ncodes,
+                        const sagms_decoder_cfg* cfg, const sagms_server_cfg* scfg, sagms_server* out);
+
+/* Queues a request (checked: SAGMS_EINVAL).  Its host buffers must stay
+ * valid until its completion has been returned.  *id may be NULL. */
+int sagms_server_submit(sagms_server s, const sagms_request* req, int64_t* id);
+
+/* One progress step (retire, then admit and launch; never blocks), then
+ * returns up to cap completions in order of completion. */
+int sagms_server_progress(sagms_server s, sagms_completion* done, int32_t cap, int32_t* ndone);
+
+/* Requests waiting, frames in launches in flight, completions not yet returned. */
+int sagms_server_pending(sagms_server s, int64_t* queued, int64_t* frames_in_flight, int64_t* completions);
+
+/* Open-loop trace replay on an idle server: request i is submitted when
+ * arrival_us[i] (non-decreasing) microseconds have passed since the call
+ * began, with that scheduled time as its submission time; progress steps
+ * run until every request has completed, and out[i] receives request i's
+ * completion.  Returns SAGMS_EHIP if no launch finishes for timeout_s. */
+int sagms_server_replay(sagms_server s, const sagms_request* reqs, const double* arrival_us, int64_t n,
+                        double timeout_s, sagms_completion* out);
+
+/* Waits for the server's streams, then frees everything it holds. */
+int sagms_server_destroy(sagms_server s);
+
 /* Message for the last non-zero status returned on this thread. */
 const char* sagms_last_error(void);
 

@@ -103,6 +103,12 @@ def lib():
             "sagms_batch_instantiate": [vp],
             "sagms_batch_tune": [vp, vp, i32, vp, i32, vp, vp],
             "sagms_batch_destroy": [vp],
+            "sagms_server_create": [vp, vp, i32, vp, vp, vp],
+            "sagms_server_submit": [vp, vp, vp],
+            "sagms_server_progress": [vp, vp, i32, vp],
+            "sagms_server_pending": [vp, vp, vp, vp],
+            "sagms_server_replay": [vp, vp, vp, i64, dbl, vp],
+            "sagms_server_destroy": [vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -343,6 +349,116 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().sagms_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- serving ---------------------------------------------------------------
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_frames_in_flight", ctypes.c_int64), ("max_frames_per_launch", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("tile_frames", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("reg_budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("nframes", ctypes.c_int32), ("synd", ctypes.c_void_p),
+                ("ehat", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("converged", ctypes.c_void_p),
+                ("deadline_us", ctypes.c_double)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
+REQ_DONE, REQ_CANCELLED = 0, 1
+# NumPy views of the C structures, for traces of millions of requests
+REQUEST_DTYPE = np.dtype({"names": ["code", "nframes", "synd", "ehat", "iters", "converged", "deadline_us"],
+                          "formats": [np.int32, np.int32, np.uint64, np.uint64, np.uint64, np.uint64, np.float64],
+                          "offsets": [0, 4, 8, 16, 24, 32, 40], "itemsize": 48})
+COMPLETION_DTYPE = np.dtype({"names": ["id", "status", "reserved", "submit_us", "admit_us", "done_us"],
+                             "formats": [np.int64, np.int32, np.int32, np.float64, np.float64, np.float64],
+                             "offsets": [0, 8, 12, 16, 24, 32], "itemsize": 40})
+
+
+def server_config(max_frames_in_flight=1 << 20, max_frames_per_launch=1 << 16, streams=4, tile_frames=8,
+                  waves_per_block=4, reg_budget=1) -> ServerConfig:
+    return ServerConfig(int(max_frames_in_flight), int(max_frames_per_launch), int(streams), int(tile_frames),
+                        int(waves_per_block), int(reg_budget), 0)
+
+
+class Server:
+    """A serving runtime over several codes (``sagms_server_*``).
+
+    Requests carry host NumPy buffers: syndromes uint64 [nframes, words_m],
+    outputs ehat uint64 [nframes, words_n], iters int32 [nframes], converged
+    uint8 [nframes].  The caller keeps them alive until completion.
+    """
+
+    def __init__(self, graphs, priors, cfg: DecoderConfig, scfg: ServerConfig = None):
+        self.graphs = list(graphs)
+        self._priors = [np.ascontiguousarray(p, dtype=np.float32) for p in priors]
+        for g, p in zip(self.graphs, self._priors):
+            if p.shape != (g.n,):
+                raise ValueError("prior of shape %s for a code with n = %d" % (p.shape, g.n))
+        n = len(self.graphs)
+        gh = (ctypes.c_void_p * max(n, 1))(*[g._h.value for g in self.graphs])
+        ph = (ctypes.c_void_p * max(n, 1))(*[p.ctypes.data for p in self._priors])
+        self._cfg = cfg
+        self._scfg = scfg if scfg is not None else server_config()
+        h = ctypes.c_void_p()
+        _check(lib().sagms_server_create(ctypes.cast(gh, ctypes.c_void_p), ctypes.cast(ph, ctypes.c_void_p), n,
+                                         ctypes.byref(cfg), ctypes.byref(self._scfg), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def _check_buffers(g, synd, ehat, iters, converged):
+        nf = synd.shape[0]
+        for arr, dt, shape, name in ((synd, np.uint64, (nf, g.words_m), "synd"), (ehat, np.uint64, (nf, g.words_n), "ehat"),
+                                     (iters, np.int32, (nf,), "iters"), (converged, np.uint8, (nf,), "converged")):
+            if arr.dtype != dt or arr.shape != shape or not arr.flags["C_CONTIGUOUS"]:
+                raise ValueError("%s must be a C-contiguous %s array of shape %s" % (name, np.dtype(dt), shape))
+        return nf
+
+    def submit(self, code, synd, ehat, iters, converged, deadline_us=0.0):
+        nf = self._check_buffers(self.graphs[code], synd, ehat, iters, converged)
+        r = Request(int(code), int(nf), synd.ctypes.data, ehat.ctypes.data, iters.ctypes.data, converged.ctypes.data,
+                    float(deadline_us))
+        rid = ctypes.c_int64()
+        _check(lib().sagms_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        return rid.value
+
+    def progress(self, cap=1024):
+        out = np.zeros(cap, dtype=COMPLETION_DTYPE)
+        n = ctypes.c_int32()
+        _check(lib().sagms_server_progress(self._h, out.ctypes.data, cap, ctypes.byref(n)))
+        return out[:n.value]
+
+    def pending(self):
+        q, f, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sagms_server_pending(self._h, ctypes.byref(q), ctypes.byref(f), ctypes.byref(c)))
+        return q.value, f.value, c.value
+
+    def replay(self, requests, arrival_us, timeout_s=30.0):
+        """requests: REQUEST_DTYPE array (pointers to live host buffers);
+        arrival_us: float64 [n], non-decreasing.  Returns COMPLETION_DTYPE [n]."""
+        requests = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+        arrival_us = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        if arrival_us.shape != (len(requests),):
+            raise ValueError("one arrival time per request")
+        out = np.zeros(len(requests), dtype=COMPLETION_DTYPE)
+        _check(lib().sagms_server_replay(self._h, requests.ctypes.data, arrival_us.ctypes.data, len(requests),
+                                         float(timeout_s), out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sagms_server_destroy(self._h)
         self._h = None
 
     def __del__(self):

@@ -6,11 +6,73 @@
 
 #include "internal.h"
 
+namespace sagms {
+
+constexpr int kDefaultQueues = 8;  // one per XCD: a block starts on queue blockIdx mod 8
+
+int mixed_tier_of_shape(int idx) {
+    for (int t = 0; t < kNumMixedTiers; ++t)
+        if (idx >= 0 && idx <= kMixedTiers[t]) return t;
+    return -1;
+}
+
+int mixed_budget_of(int tier, int requested) { return requested == 1 && mixed_has_budget(tier, 1) ? 1 : 0; }
+
+int mixed_waves_of(int tier, int requested) {
+    int w = requested;
+    while (w > 1 && (size_t)w * mixed_words(tier) * sizeof(float) > 65536) w /= 2;
+    return w;
+}
+
+int OccupancyCache::get(int tier, int budget, int mt, int wpb, int* out) {
+    const auto key = std::make_tuple(tier, budget, mt, wpb);
+    auto it = blocks.find(key);
+    if (it == blocks.end()) {
+        int n = 0;
+        int rc = mixed_max_blocks(tier, budget, mt, wpb, &n);
+        if (rc) return rc;
+        it = blocks.emplace(key, n).first;
+    }
+    *out = it->second;
+    return SAGMS_OK;
+}
+
+int launch_segments(const MixedSegment* segs, int nseg, int tier, const MixedLaunch& p, int num_cu, int mt,
+                    uint32_t* queues, OccupancyCache* occ, hipStream_t st) {
+    if (nseg < 1 || nseg > kMaxSegments) return fail(SAGMS_EINVAL, "segment count out of range (internal)");
+    MixedArgs m{};
+    for (int s = 0; s < nseg; ++s) m.segs[s] = segs[s];
+    m.queues = queues;
+    m.nseg = nseg;
+    m.tile_frames = p.tile_frames;
+    m.words = mixed_words(tier);
+    int64_t tiles = 0;
+    for (int s = 0; s < nseg; ++s) {
+        if (mixed_tier_of_shape(segs[s].shape) > tier) return fail(SAGMS_EINVAL, "segment above the kernel's tier (internal)");
+        tiles += (segs[s].a.nframes + p.tile_frames - 1) / p.tile_frames;
+        m.tile_end[s] = tiles;
+    }
+    if (tiles == 0) return SAGMS_OK;
+    if (tiles > 0x7fffffffLL) return fail(SAGMS_EINVAL, "too many tiles for one launch: raise tile_frames");
+    m.ntiles = tiles;
+    m.nq = (int)std::min<int64_t>(kDefaultQueues, tiles);
+    const int budget = mixed_budget_of(tier, p.reg_budget);
+    const int wpb = mixed_waves_of(tier, p.waves_per_block);
+    int per_cu = 0;
+    int rc = occ->get(tier, budget, mt, wpb, &per_cu);
+    if (rc) return rc;
+    if (per_cu < 1) return fail(SAGMS_EUNSUPPORTED, "mixed kernel of tier %d does not fit a compute unit", tier);
+    if (p.blocks_per_cu > 0) per_cu = std::min(per_cu, p.blocks_per_cu);
+    int64_t blocks = (int64_t)per_cu * num_cu;
+    blocks = std::min<int64_t>(blocks, (tiles + wpb - 1) / wpb);
+    return launch_mixed(tier, budget, mt, m, (int)blocks, wpb, st);
+}
+
+}  // namespace sagms
+
 using namespace sagms;
 
 namespace {
-
-constexpr int kDefaultQueues = 8;  // one per XCD: a block starts on queue blockIdx mod 8
 
 struct Batch {
     int device = 0;
@@ -26,15 +88,8 @@ struct Batch {
     sagms_plan plan{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // resident blocks per CU by (tier, register budget, waves per block)
-    std::map<std::tuple<int, int, int>, int> occupancy;
+    OccupancyCache occupancy;
 };
-
-int tier_of_shape(int idx) {
-    for (int t = 0; t < kNumMixedTiers; ++t)
-        if (idx <= kMixedTiers[t]) return t;
-    return -1;
-}
 
 void drop_graph(Batch* b) {
     if (b->exec) hipGraphExecDestroy(b->exec);
@@ -43,7 +98,7 @@ void drop_graph(Batch* b) {
     b->graph = nullptr;
 }
 
-int check_plan(const Batch* b, const sagms_plan* p) {
+int check_plan(const Batch*, const sagms_plan* p) {
     if (!p) return fail(SAGMS_EINVAL, "plan is null");
     if (p->kind < SAGMS_PLAN_SINGLE || p->kind > SAGMS_PLAN_PER_CODE) return fail(SAGMS_EINVAL, "unknown plan kind %d", p->kind);
     if (p->tile_frames < 1 || p->tile_frames > 1024) return fail(SAGMS_EINVAL, "tile_frames must lie in [1, 1024]");
@@ -56,59 +111,18 @@ int check_plan(const Batch* b, const sagms_plan* p) {
     return SAGMS_OK;
 }
 
-// Waves per block of a tier: the plan's, halved until the block's LDS
-// slices fit 64 KiB.
-int waves_of(int tier, int requested) {
-    int w = requested;
-    while (w > 1 && (size_t)w * mixed_words(tier) * sizeof(float) > 65536) w /= 2;
-    return w;
-}
-
-// The tight register budget where the tier has one, else the compiler's.
-int budget_of(int tier, int requested) { return requested == 1 && mixed_has_budget(tier, 1) ? 1 : 0; }
-
 int blocks_per_cu(Batch* b, int tier, int* out) {
-    const int budget = budget_of(tier, b->plan.reg_budget);
-    const int wpb = waves_of(tier, b->plan.waves_per_block);
-    const auto key = std::make_tuple(tier, budget, wpb);
-    auto it = b->occupancy.find(key);
-    if (it == b->occupancy.end()) {
-        int n = 0;
-        int rc = mixed_max_blocks(tier, budget, b->mt, wpb, &n);
-        if (rc) return rc;
-        it = b->occupancy.emplace(key, n).first;
-    }
-    *out = it->second;
-    return SAGMS_OK;
+    const int budget = mixed_budget_of(tier, b->plan.reg_budget);
+    const int wpb = mixed_waves_of(tier, b->plan.waves_per_block);
+    return b->occupancy.get(tier, budget, b->mt, wpb, out);
 }
 
 // One persistent launch over segments [s0, s1) with the kernel of `tier`.
 int launch_group(Batch* b, int s0, int s1, int tier, hipStream_t st) {
     const sagms_plan& p = b->plan;
-    MixedArgs m{};
-    for (int s = s0; s < s1; ++s) m.segs[s - s0] = b->segs[s];
-    m.queues = b->d_queues + (size_t)tier * kMaxQueues * kQueueStride;
-    m.nseg = s1 - s0;
-    m.tile_frames = p.tile_frames;
-    m.words = mixed_words(tier);
-    int64_t tiles = 0;
-    for (int s = s0; s < s1; ++s) {
-        tiles += (b->segs[s].a.nframes + p.tile_frames - 1) / p.tile_frames;
-        m.tile_end[s - s0] = tiles;
-    }
-    if (tiles == 0) return SAGMS_OK;
-    if (tiles > 0x7fffffffLL) return fail(SAGMS_EINVAL, "too many tiles for one launch: raise tile_frames");
-    m.ntiles = tiles;
-    m.nq = (int)std::min<int64_t>(kDefaultQueues, tiles);
-    int per_cu = 0;
-    int rc = blocks_per_cu(b, tier, &per_cu);
-    if (rc) return rc;
-    if (per_cu < 1) return fail(SAGMS_EUNSUPPORTED, "mixed kernel of tier %d does not fit a compute unit", tier);
-    if (p.blocks_per_cu > 0) per_cu = std::min(per_cu, p.blocks_per_cu);
-    const int wpb = waves_of(tier, p.waves_per_block);
-    int64_t blocks = (int64_t)per_cu * b->num_cu;
-    blocks = std::min<int64_t>(blocks, (tiles + wpb - 1) / wpb);
-    return launch_mixed(tier, budget_of(tier, p.reg_budget), b->mt, m, (int)blocks, wpb, st);
+    MixedLaunch L{p.tile_frames, p.waves_per_block, p.blocks_per_cu, p.reg_budget};
+    return launch_segments(b->segs.data() + s0, s1 - s0, tier, L, b->num_cu, b->mt,
+                           b->d_queues + (size_t)tier * kMaxQueues * kQueueStride, &b->occupancy, st);
 }
 
 int enqueue(Batch* b, hipStream_t st) {
@@ -188,7 +202,7 @@ int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_deco
         const DecodeShape& sh = reinterpret_cast<Graph*>(segs[s].graph)->shape;
         return sh.cpl * sh.dc + sh.vpl * sh.dv;
     };
-    auto tier = [&](int s) { return tier_of_shape(shape_index(reinterpret_cast<Graph*>(segs[s].graph)->shape)); };
+    auto tier = [&](int s) { return mixed_tier_of_shape(shape_index(reinterpret_cast<Graph*>(segs[s].graph)->shape)); };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         if (tier(x) != tier(y)) return tier(x) > tier(y);
         return cost(x) > cost(y);
@@ -315,7 +329,8 @@ int sagms_batch_tune(sagms_batch bh, void* stream, int32_t reps, sagms_tune_resu
                     // a waves-per-block value that every launched tier halves is a duplicate
                     bool dup = true;
                     for (int t : b->tier)
-                        if ((kind == SAGMS_PLAN_TIERED || t == b->tier.front()) && waves_of(t, wpb) == wpb) dup = false;
+                        if ((kind == SAGMS_PLAN_TIERED || t == b->tier.front()) && mixed_waves_of(t, wpb) == wpb)
+                            dup = false;
                     if (dup) continue;
                     sagms_plan p{kind, tf, wpb, 0, budget, 0};
                     if (check_plan(b, &p) == SAGMS_OK) cands.push_back(p);

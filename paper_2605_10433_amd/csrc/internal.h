@@ -185,6 +185,30 @@ int mixed_max_blocks(int tier, int budget, int mt, int waves_per_block, int* out
 // SAGMS; BP has no mixed kernel).
 int launch_mixed(int tier, int budget, int mt, const MixedArgs& m, int blocks, int waves_per_block, hipStream_t st);
 
+// Register class of a shape index (-1 if none).
+int mixed_tier_of_shape(int shape_idx);
+// The tight register budget where the tier has one, else the compiler's.
+int mixed_budget_of(int tier, int requested);
+// Waves per block of a tier: the requested number, halved until the block's
+// LDS slices fit 64 KiB.
+int mixed_waves_of(int tier, int requested);
+
+// Resident blocks per CU of the mixed kernels, queried once per key.
+struct OccupancyCache {
+    std::map<std::tuple<int, int, int, int>, int> blocks;
+    int get(int tier, int budget, int mt, int waves_per_block, int* out);
+};
+
+struct MixedLaunch {
+    int tile_frames, waves_per_block, blocks_per_cu, reg_budget;
+};
+
+// One persistent launch over nseg segments (all of register class <= tier)
+// on stream st: grid = resident capacity (capped by blocks_per_cu when > 0,
+// and by the number of tiles); queues = this launch's own counter block.
+int launch_segments(const MixedSegment* segs, int nseg, int tier, const MixedLaunch& p, int num_cu, int mt,
+                    uint32_t* queues, OccupancyCache* occ, hipStream_t st);
+
 
 struct SampleArgs {
     const int32_t* cols;

@@ -184,3 +184,53 @@ def test_plan_structures():
     assert ctypes.sizeof(sagms.Plan) == 24 and ctypes.sizeof(sagms.Segment) == 64
     with pytest.raises(ValueError):
         sagms.plan("bogus")
+
+
+def test_server_create_and_calls_check_before_device_work():
+    L = sagms.lib()
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    prior = np.full(g.n, 3.0, dtype=np.float32)
+    gh = (ctypes.c_void_p * 1)(g._h.value)
+    ph = (ctypes.c_void_p * 1)(prior.ctypes.data)
+    cfg = sagms.decoder_config("sagms")
+
+    def rc(scfg, n=1, graphs=gh, priors=ph, c=cfg):
+        h = ctypes.c_void_p()
+        return L.sagms_server_create(ctypes.cast(graphs, ctypes.c_void_p) if graphs is not None else None,
+                                     ctypes.cast(priors, ctypes.c_void_p) if priors is not None else None, n,
+                                     ctypes.byref(c), ctypes.byref(scfg), ctypes.byref(h))
+
+    S = sagms.server_config
+    assert rc(S(), graphs=None) == sagms.EINVAL
+    assert rc(S(), priors=None) == sagms.EINVAL
+    assert rc(S(), n=0) == sagms.EINVAL
+    assert rc(S(), n=17) == sagms.EINVAL
+    assert rc(S(max_frames_per_launch=0)) == sagms.EINVAL
+    assert rc(S(max_frames_per_launch=1 << 25)) == sagms.EINVAL
+    assert rc(S(max_frames_in_flight=100, max_frames_per_launch=200)) == sagms.EINVAL
+    assert rc(S(streams=0)) == sagms.EINVAL and rc(S(streams=9)) == sagms.EINVAL
+    assert rc(S(tile_frames=0)) == sagms.EINVAL and rc(S(waves_per_block=3)) == sagms.EINVAL
+    assert rc(S(reg_budget=2)) == sagms.EINVAL
+    assert rc(S(), c=sagms.decoder_config("bp")) == sagms.EUNSUPPORTED
+    assert rc(S(), graphs=(ctypes.c_void_p * 1)(None)) == sagms.EINVAL
+    assert rc(S(), priors=(ctypes.c_void_p * 1)(None)) == sagms.EINVAL
+    assert L.sagms_server_submit(None, None, None) == sagms.EINVAL
+    assert L.sagms_server_progress(None, None, 0, None) == sagms.EINVAL
+    assert L.sagms_server_pending(None, None, None, None) == sagms.EINVAL
+    assert L.sagms_server_replay(None, None, None, 0, 1.0, None) == sagms.EINVAL
+    assert L.sagms_server_destroy(None) == sagms.EINVAL
+
+
+def test_serving_structures_and_trace():
+    assert ctypes.sizeof(sagms.Request) == sagms.REQUEST_DTYPE.itemsize == 48
+    assert ctypes.sizeof(sagms.Completion) == sagms.COMPLETION_DTYPE.itemsize == 40
+    assert ctypes.sizeof(sagms.ServerConfig) == 32
+    for name, _ in sagms.Request._fields_:
+        assert sagms.REQUEST_DTYPE.fields[name][1] == getattr(sagms.Request, name).offset
+    for name, _ in sagms.Completion._fields_:
+        assert sagms.COMPLETION_DTYPE.fields[name][1] == getattr(sagms.Completion, name).offset
+    code, size, t = workloads.serve_trace(1e6, 20000)
+    assert (np.diff(t) >= 0).all() and size.min() >= 1 and size.max() <= 64
+    assert set(np.unique(code)) == set(range(5))
+    assert abs(np.mean(np.diff(t)) - 1.0) < 0.05                 # mean gap 1 us at 1e6 / s
+    assert abs(size.mean() - 32.5) < 1.0

@@ -43,6 +43,31 @@ MIX_SEED = 3
 PRECISION_P = [0.03, 0.05]
 
 
+# The serving workload: requests of U{1..64} syndromes from one of five codes
+# chosen uniformly, Poisson arrivals (seed 5), p = 0.04, l_max = 100.
+SERVE_CODES = ["G63", "G127", "G255w3", "G255w4", "G511w5"]
+SERVE_P = 0.04
+SERVE_LMAX = 100
+SERVE_SEED = 5
+SERVE_MAX_FRAMES = 64
+SERVE_LOADS = [0.5, 0.8]     # offered load, fraction of the measured batch throughput
+
+
+def serve_trace(rate_per_s: float, nreq: int, seed: int = SERVE_SEED):
+    """(code index, frames, arrival time in us) of nreq requests: Poisson
+    arrivals at rate_per_s, codes uniform over SERVE_CODES, sizes U{1..64}."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1e6 / rate_per_s, nreq)
+    code = rng.integers(0, len(SERVE_CODES), nreq).astype(np.int32)
+    size = rng.integers(1, SERVE_MAX_FRAMES + 1, nreq).astype(np.int32)
+    return code, size, np.cumsum(gaps)
+
+
+def serve_stream(i: int) -> int:
+    """Philox stream of the frame pool of serving code i."""
+    return 200 + i
+
+
 def mix_stream(i: int, p: float) -> int:
     """Philox stream of mix segment i at noise level p (distinct per pair)."""
     return 100 + 10 * i + int(round(p * 100))
