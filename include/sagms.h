@@ -296,8 +296,10 @@ int sagms_batch_destroy(sagms_batch b);
  * FIFO per register class of the codes.  Each progress step first retires
  * finished launches (their outputs are copied to the requests' host buffers
  * and their completions recorded), then, while one of the server's streams
- * is free, takes the class whose oldest waiting request is oldest and admits
- * requests from it in order while the launch holds at most
+ * is free, takes the class whose oldest waiting request is oldest among the
+ * classes ready to launch (min_launch_frames waiting, or max_wait_us
+ * exceeded, or no launch in flight) and admits requests from it in order
+ * while the launch holds at most
  * max_frames_per_launch frames and all launches in flight at most
  * max_frames_in_flight frames (the device-memory budget); the admitted
  * frames go to the GPU as one copy, one persistent mixed-code launch and one
@@ -311,11 +313,15 @@ typedef struct sagms_server_s* sagms_server;
 typedef struct {
     int64_t max_frames_in_flight;  /* frames in all launches in flight, >= max_frames_per_launch */
     int32_t max_frames_per_launch; /* 1 .. 2^24; also the largest request    */
+    int32_t min_launch_frames;     /* a class is launched once it has this many
+                                      frames waiting (0 .. max_frames_per_launch), */
+    double max_wait_us;            /* or once its oldest request has waited this
+                                      long (>= 0), or at once when nothing is
+                                      in flight                               */
     int32_t streams;               /* launches in flight at once, 1 .. 8     */
     int32_t tile_frames;           /* persistent-kernel tile, 1 .. 1024      */
     int32_t waves_per_block;       /* 1, 2 or 4 (halved where LDS needs it)  */
     int32_t reg_budget;            /* 0 or 1, as in sagms_plan               */
-    int32_t reserved;              /* must be 0                              */
 } sagms_server_cfg;
 
 typedef struct {

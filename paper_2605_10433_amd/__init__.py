@@ -361,8 +361,9 @@ class Batch:
 # ---- serving ---------------------------------------------------------------
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_frames_in_flight", ctypes.c_int64), ("max_frames_per_launch", ctypes.c_int32),
+                ("min_launch_frames", ctypes.c_int32), ("max_wait_us", ctypes.c_double),
                 ("streams", ctypes.c_int32), ("tile_frames", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("reg_budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("reg_budget", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -386,10 +387,10 @@ COMPLETION_DTYPE = np.dtype({"names": ["id", "status", "reserved", "submit_us", 
                              "offsets": [0, 8, 12, 16, 24, 32], "itemsize": 40})
 
 
-def server_config(max_frames_in_flight=1 << 20, max_frames_per_launch=1 << 16, streams=4, tile_frames=8,
-                  waves_per_block=4, reg_budget=1) -> ServerConfig:
-    return ServerConfig(int(max_frames_in_flight), int(max_frames_per_launch), int(streams), int(tile_frames),
-                        int(waves_per_block), int(reg_budget), 0)
+def server_config(max_frames_in_flight=1 << 20, max_frames_per_launch=1 << 16, min_launch_frames=0, max_wait_us=0.0,
+                  streams=4, tile_frames=8, waves_per_block=4, reg_budget=1) -> ServerConfig:
+    return ServerConfig(int(max_frames_in_flight), int(max_frames_per_launch), int(min_launch_frames),
+                        float(max_wait_us), int(streams), int(tile_frames), int(waves_per_block), int(reg_budget))
 
 
 class Server:

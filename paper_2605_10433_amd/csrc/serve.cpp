@@ -70,6 +70,7 @@ struct Server {
     std::vector<Slot> slots;
     std::deque<sagms_completion> completed;
     int64_t next_id = 0, in_flight = 0, queued = 0, with_deadline = 0;
+    int64_t lane_frames[kNumMixedTiers] = {};  // frames waiting per class
     OccupancyCache occ;
     Clock::time_point t0;
     size_t in_bytes = 0, out_bytes = 0;
@@ -125,6 +126,7 @@ int launch(Server* s, Slot& x, int tier, double t) {
     int64_t frames = 0;
     while (!q.empty() && frames + q.front().r.nframes <= cap) {
         frames += q.front().r.nframes;
+        s->lane_frames[tier] -= q.front().r.nframes;
         if (q.front().r.deadline_us > 0.0) --s->with_deadline;
         x.reqs.push_back(q.front());
         q.pop_front();
@@ -204,10 +206,12 @@ int progress(Server* s, int* retired) {
     }
     // cancel waiting requests whose admission deadline has passed
     if (s->with_deadline > 0)
-        for (std::deque<Req>& q : s->lane)
+        for (int k = 0; k < kNumMixedTiers; ++k) {
+            std::deque<Req>& q = s->lane[k];
             for (auto it = q.begin(); it != q.end();) {
                 if (it->r.deadline_us > 0.0 && t - it->submit_us > it->r.deadline_us) {
                     s->completed.push_back(sagms_completion{it->id, SAGMS_REQ_CANCELLED, 0, it->submit_us, -1.0, t});
+                    s->lane_frames[k] -= it->r.nframes;
                     it = q.erase(it);
                     --s->queued;
                     --s->with_deadline;
@@ -215,12 +219,16 @@ int progress(Server* s, int* retired) {
                     ++it;
                 }
             }
+        }
     for (Slot& x : s->slots) {
         if (x.busy) continue;
         int tier = -1;
-        for (int k = 0; k < kNumMixedTiers; ++k)
-            if (!s->lane[k].empty() && (tier < 0 || s->lane[k].front().submit_us < s->lane[tier].front().submit_us))
-                tier = k;
+        for (int k = 0; k < kNumMixedTiers; ++k) {
+            if (s->lane[k].empty()) continue;
+            const bool ready = s->in_flight == 0 || s->lane_frames[k] >= s->scfg.min_launch_frames ||
+                               t - s->lane[k].front().submit_us >= s->scfg.max_wait_us;
+            if (ready && (tier < 0 || s->lane[k].front().submit_us < s->lane[tier].front().submit_us)) tier = k;
+        }
         if (tier < 0) break;
         if (s->lane[tier].front().r.nframes > s->scfg.max_frames_in_flight - s->in_flight) break;  // budget full
         int rc = launch(s, x, tier, t);
@@ -243,6 +251,7 @@ int check_request(const Server* s, const sagms_request* r) {
 void push(Server* s, const sagms_request* r, double submit_us, int64_t* id) {
     Req q{s->next_id++, *r, submit_us};
     s->lane[s->codes[r->code].tier].push_back(q);
+    s->lane_frames[s->codes[r->code].tier] += r->nframes;
     ++s->queued;
     if (r->deadline_us > 0.0) ++s->with_deadline;
     if (id) *id = q.id;
@@ -272,7 +281,9 @@ int sagms_server_create(const sagms_graph* graphs, const float* const* llr0_host
     if (scfg->waves_per_block != 1 && scfg->waves_per_block != 2 && scfg->waves_per_block != 4)
         return fail(SAGMS_EINVAL, "waves_per_block must be 1, 2 or 4");
     if (scfg->reg_budget != 0 && scfg->reg_budget != 1) return fail(SAGMS_EINVAL, "reg_budget must be 0 or 1");
-    if (scfg->reserved != 0) return fail(SAGMS_EINVAL, "reserved field must be 0");
+    if (scfg->min_launch_frames < 0 || scfg->min_launch_frames > scfg->max_frames_per_launch)
+        return fail(SAGMS_EINVAL, "min_launch_frames must lie in [0, max_frames_per_launch]");
+    if (!(scfg->max_wait_us >= 0.0)) return fail(SAGMS_EINVAL, "max_wait_us must be >= 0");
     for (int c = 0; c < ncodes; ++c) {
         Graph* g = reinterpret_cast<Graph*>(graphs[c]);
         if (!g) return fail(SAGMS_EINVAL, "code %d: null graph", c);

@@ -211,6 +211,9 @@ def test_server_create_and_calls_check_before_device_work():
     assert rc(S(streams=0)) == sagms.EINVAL and rc(S(streams=9)) == sagms.EINVAL
     assert rc(S(tile_frames=0)) == sagms.EINVAL and rc(S(waves_per_block=3)) == sagms.EINVAL
     assert rc(S(reg_budget=2)) == sagms.EINVAL
+    assert rc(S(min_launch_frames=-1)) == sagms.EINVAL
+    assert rc(S(max_frames_per_launch=64, min_launch_frames=65, max_frames_in_flight=64)) == sagms.EINVAL
+    assert rc(S(max_wait_us=-1.0)) == sagms.EINVAL
     assert rc(S(), c=sagms.decoder_config("bp")) == sagms.EUNSUPPORTED
     assert rc(S(), graphs=(ctypes.c_void_p * 1)(None)) == sagms.EINVAL
     assert rc(S(), priors=(ctypes.c_void_p * 1)(None)) == sagms.EINVAL
@@ -224,7 +227,7 @@ def test_server_create_and_calls_check_before_device_work():
 def test_serving_structures_and_trace():
     assert ctypes.sizeof(sagms.Request) == sagms.REQUEST_DTYPE.itemsize == 48
     assert ctypes.sizeof(sagms.Completion) == sagms.COMPLETION_DTYPE.itemsize == 40
-    assert ctypes.sizeof(sagms.ServerConfig) == 32
+    assert ctypes.sizeof(sagms.ServerConfig) == 40
     for name, _ in sagms.Request._fields_:
         assert sagms.REQUEST_DTYPE.fields[name][1] == getattr(sagms.Request, name).offset
     for name, _ in sagms.Completion._fields_:
