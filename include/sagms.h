@@ -146,6 +146,20 @@ int sagms_destroy_graph(sagms_graph g);
  * rounded to float.  Returns NaN for p outside (0, 0.75). */
 float sagms_prior_llr(double p);
 
+/* BP-matching ratio of eq. (alphastar): the scale that makes the min-sum
+ * check output equal the BP output when all d_c - 1 incoming magnitudes
+ * equal L0, (2 / L0) atanh(tanh(L0 / 2)^(d_c - 1)), evaluated in double
+ * without cancellation for large L0.  NaN unless L0 > 0 and d_c >= 2. */
+double sagms_alpha_star(double l0, int32_t dc);
+
+/* Derived SAGMS gains (Corollary 1 with the ratio of the Section V setup):
+ * alpha_max = alpha*(L0, d_c), alpha_min = ratio * alpha_max, and eta =
+ * 1 / alpha_max (the largest value with alpha_max * eta <= 1, Section III)
+ * when eta <= 0, else the given eta.  Writes kind = SAGMS and the three
+ * gains into *cfg, leaving its other fields unchanged.  SAGMS_EINVAL unless
+ * L0 > 0, d_c >= 2, 0 < ratio <= 1 and alpha_max * eta <= 1. */
+int sagms_derive_gains(double l0, int32_t dc, double ratio, double eta, sagms_decoder_cfg* cfg);
+
 /* ---- device entry points --------------------------------------------- */
 
 /* Depolarizing errors and their syndromes (Section II, channel and syndrome).

@@ -53,6 +53,11 @@ Arithmetic modes
             v2c       = half(posterior - c2v)       (FP32 difference)
             CN output = sign * half(float32(gain) * exclusive min)
             posterior = FP32 sum as in "fp32" (the first v2c is half(L0))
+          The prior is first put on the grid of step 2^-24 (values of
+          magnitude >= 1 are already on it): every half is a multiple of
+          2^-24, so every posterior and v2c is one too, and a v2c is either
+          +0 or at least 2^-24 in magnitude -- it never rounds to -0, and its
+          sign (sgn(0) = +1) is the sign of the unrounded FP32 difference.
   "int6"  6-bit magnitude plus sign on a grid of step 1/4 (range +-15.75):
           q(x) = clip(round_half_even(4 x), -63, 63) / 4; the prior is
           quantized too, L0' = q(L0), so posteriors L0' + sum c2v are exact
@@ -72,6 +77,14 @@ import numpy as np
 
 KINDS = ("ms", "sms", "sagms", "bp")
 ARITH = ("fp64", "fp32", "fp16", "int6")
+
+
+def grid24(x):
+    """x rounded to a multiple of 2^-24 (nearest even), -0 read as +0."""
+    x = np.asarray(x, dtype=np.float32)
+    small = np.abs(x) < 1.0
+    r = np.where(small, np.rint(x * np.float32(2.0 ** 24)) * np.float32(2.0 ** -24), x).astype(np.float32)
+    return r + np.float32(0.0)
 
 
 def quantize(x, arith):
@@ -254,7 +267,9 @@ def decode(g: TannerGraph, synd, llr0, params: DecoderParams, arith: str = "fp64
     m, n, E = g.m, g.n, g.E
     L0 = np.asarray(llr0, dtype=np.float64).astype(dt) + dt(0.0)   # -0 -> +0
     if arith == "int6":
-        L0 = quantize(L0, arith)
+        L0 = quantize(L0, arith) + dt(0.0)                          # a prior rounding to -0 reads as +0
+    if arith == "fp16":
+        L0 = grid24(L0)
     if L0.shape != (n,):
         raise ValueError("llr0 must have n entries")
 

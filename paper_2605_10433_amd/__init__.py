@@ -118,6 +118,10 @@ def lib():
         L.sagms_last_error.restype = ctypes.c_char_p
         L.sagms_prior_llr.argtypes = [dbl]
         L.sagms_prior_llr.restype = ctypes.c_float
+        L.sagms_alpha_star.argtypes = [dbl, i32]
+        L.sagms_alpha_star.restype = ctypes.c_double
+        L.sagms_derive_gains.argtypes = [dbl, i32, dbl, dbl, vp]
+        L.sagms_derive_gains.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -135,6 +139,17 @@ def _check(rc):
 
 def prior_llr(p: float) -> float:
     return float(lib().sagms_prior_llr(float(p)))
+
+
+def alpha_star(l0: float, dc: int) -> float:
+    return float(lib().sagms_alpha_star(float(l0), int(dc)))
+
+
+def derived_config(l0, dc, ratio=0.6, eta=0.0, lmax=100, frames_per_wave=0, precision="fp32") -> "DecoderConfig":
+    """SAGMS with the derived gains of sagms_derive_gains (eta <= 0: 1 / alpha_max)."""
+    cfg = decoder_config("sagms", lmax=lmax, frames_per_wave=frames_per_wave, precision=precision)
+    _check(lib().sagms_derive_gains(float(l0), int(dc), float(ratio), float(eta), ctypes.byref(cfg)))
+    return cfg
 
 
 def decoder_config(kind="sagms", lmax=100, alpha=0.75, alpha_min=0.30, alpha_max=0.50, eta=1.10,

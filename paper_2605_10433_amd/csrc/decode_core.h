@@ -104,13 +104,35 @@ __device__ __forceinline__ uint32_t xor_signs(const float (&x)[N], uint32_t init
 // Message formats: FP32; FP16 (every message saturated to +-65504 and
 // rounded to half, posteriors FP32); INT6 (sign + 6-bit magnitude on a grid
 // of step 1/4, saturating at +-63 steps; the prior is quantized as well, so
-// posterior sums are exact).  Messages are held as FP32 values on the grid.
+// posterior sums are exact).  Messages are held as FP32 values.
+//
+// Only the check outputs are rounded.  Both roundings are monotone and keep
+// the sign, so the minimum, the second minimum and the sign parity of the
+// rounded v2c messages are the rounded minimum, second minimum and parity of
+// the unrounded ones: the check output sign * q(gain * q(exclusive min)) is
+// the same either way.  (The FP16 prior lies on the 2^-24 grid, so a v2c is
+// +0 or at least 2^-24 in magnitude and never rounds to a signed zero; INT6
+// v2c messages are exact grid values.)
 template <int MT>
 __device__ __forceinline__ float quantize(float x) {
     if constexpr (MT == SAGMS_MSG_FP16) {
         return __half2float(__float2half_rn(__builtin_amdgcn_fmed3f(x, -65504.0f, 65504.0f)));
     } else if constexpr (MT == SAGMS_MSG_INT6) {
         return __builtin_amdgcn_fmed3f(rintf(x * 4.0f), -63.0f, 63.0f) * 0.25f;
+    } else {
+        return x;
+    }
+}
+
+// The prior as the decoder uses it: -0 read as +0; INT6 puts it on the
+// message grid, FP16 on the grid of step 2^-24 (magnitudes >= 1 already are).
+template <int MT>
+__device__ __forceinline__ float prior(float x) {
+    x = x + 0.0f;
+    if constexpr (MT == SAGMS_MSG_INT6) {
+        return quantize<MT>(x) + 0.0f;
+    } else if constexpr (MT == SAGMS_MSG_FP16) {
+        return (fabsf(x) < 1.0f ? rintf(x * 16777216.0f) * 0x1.0p-24f : x) + 0.0f;
     } else {
         return x;
     }
@@ -142,7 +164,14 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, uin
         // parity; per edge: compare, select, and one 3-input bit operation
         // applying the edge's own sign.  The empty asm keeps the compiler
         // from folding the select back into one product per edge.
-        uint32_t S1 = bits(quantize<MT>(alpha * m1)) | par, S2 = bits(quantize<MT>(alpha * m2)) | par;
+        uint32_t S1, S2;
+        if constexpr (MT == SAGMS_MSG_FP32) {
+            S1 = bits(alpha * m1) | par;
+            S2 = bits(alpha * m2) | par;
+        } else {
+            S1 = bits(quantize<MT>(alpha * quantize<MT>(m1))) | par;
+            S2 = bits(quantize<MT>(alpha * quantize<MT>(m2))) | par;
+        }
         asm("" : "+v"(S1), "+v"(S2));
 #pragma unroll
         for (int p = 0; p < DC; ++p) {
@@ -175,7 +204,7 @@ struct WaveDecoder {
 #pragma unroll
         for (int k = 0; k < VPL; ++k) {
             int j = k * 64 + lane;
-            L0[k] = j < a.n ? quantize<MT == SAGMS_MSG_INT6 ? MT : SAGMS_MSG_FP32>(a.llr0[j] + 0.0f) : __builtin_inff();
+            L0[k] = j < a.n ? prior<MT>(a.llr0[j]) : __builtin_inff();
         }
         // gain table: in registers (lane w holds entry w) when m <= 64, else in LDS
         gsl = a.gains[2 * lane];
@@ -226,7 +255,7 @@ struct WaveDecoder {
 #pragma unroll
                 for (int p = 0; p < DC; ++p) {
                     pj[p] = lds[caddr[k][p]];
-                    v[k][p] = quantize<MT>(pj[p] - c2v[k][p]);
+                    v[k][p] = pj[p] - c2v[k][p];  // rounded only through the check output
                 }
                 res[k] = xor_signs<DC>(pj, sb[k]);
                 w += __builtin_popcountll(ballot(res[k] != 0));

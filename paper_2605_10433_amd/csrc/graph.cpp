@@ -445,6 +445,38 @@ int sagms_destroy_graph(sagms_graph gh) {
     return SAGMS_OK;
 }
 
+double sagms_alpha_star(double l0, int32_t dc) {
+    if (!(l0 > 0.0) || dc < 2) return std::nan("");
+    // y = tanh(L0/2)^(dc-1) from log tanh(L0/2) = log1p(-2 / (e^L0 + 1));
+    // 2 atanh(y) = log1p(y) - log(1 - y), with 1 - y = -expm1((dc-1) log tanh)
+    // kept exact near y = 1 and log1p(-y) used for small y
+    const double lt = std::log1p(-2.0 / (std::exp(l0) + 1.0));
+    const double y = std::exp((dc - 1) * lt);
+    const double one_minus_y = -std::expm1((dc - 1) * lt);
+    if (!(one_minus_y > 0.0)) return 1.0;  // y rounds to 1 only as L0 -> inf, where alpha* -> 1
+    const double two_atanh = std::log1p(y) - (y < 0.5 ? std::log1p(-y) : std::log(one_minus_y));
+    return two_atanh / l0;
+}
+
+int sagms_derive_gains(double l0, int32_t dc, double ratio, double eta, sagms_decoder_cfg* cfg) {
+    if (!cfg) return fail(SAGMS_EINVAL, "cfg is null");
+    if (!(l0 > 0.0) || dc < 2) return fail(SAGMS_EINVAL, "need L0 > 0 and d_c >= 2");
+    if (!(ratio > 0.0 && ratio <= 1.0)) return fail(SAGMS_EINVAL, "ratio must lie in (0, 1]");
+    const double amax = sagms_alpha_star(l0, dc);
+    double e = eta;
+    if (!(eta > 0.0)) {
+        e = 1.0 / amax;
+        while (amax * e > 1.0) e = std::nextafter(e, 0.0);  // the largest eta with alpha_max * eta <= 1
+    }
+    if (!(amax * e <= 1.0)) return fail(SAGMS_EINVAL, "alpha_max * eta = %g exceeds 1", amax * e);
+    if (!(e >= 1.0)) return fail(SAGMS_EINVAL, "eta must be >= 1");
+    cfg->kind = SAGMS_SAGMS;
+    cfg->alpha_max = amax;
+    cfg->alpha_min = ratio * amax;
+    cfg->eta = e;
+    return SAGMS_OK;
+}
+
 float sagms_prior_llr(double p) {
     if (!(p > 0.0 && p < 0.75)) return NAN;
     double q = 2.0 * p / 3.0;

@@ -237,3 +237,46 @@ def test_serving_structures_and_trace():
     assert set(np.unique(code)) == set(range(5))
     assert abs(np.mean(np.diff(t)) - 1.0) < 0.05                 # mean gap 1 us at 1e6 / s
     assert abs(size.mean() - 32.5) < 1.0
+
+
+@pytest.mark.parametrize("dc", [2, 4, 6, 8, 10, 16])
+def test_alpha_star_matches_oracle(dc):
+    from oracle import analysis
+    for l0 in (0.5, 1.0, 2.639, 3.36730, 3.597, 4.304, 8.0, 15.0):
+        # the oracle's direct form loses digits as tanh(L0/2) -> 1 (about 1e-12 at L0 = 15)
+        tol = 1e-12 if l0 < 8 else 1e-10
+        assert sagms.alpha_star(l0, dc) == pytest.approx(analysis.alpha_star(l0, dc), rel=tol)
+        if dc == 2:
+            assert sagms.alpha_star(l0, dc) == pytest.approx(1.0, abs=4e-16)   # atanh(tanh(x)) = x
+    # where the direct form overflows: the large-L0 form 1 - ln(d_c - 1) / L0 is exact to O(e^-L0)
+    assert sagms.alpha_star(40.0, dc) == pytest.approx(analysis.alpha_star_approx(40.0, dc), rel=1e-13)
+    assert np.isnan(sagms.alpha_star(0.0, dc)) and np.isnan(sagms.alpha_star(3.0, 1))
+
+
+def test_derived_gains():
+    from oracle import analysis
+    l0 = channel.prior_llr(0.05)
+    cfg = sagms.derived_config(l0, 10)
+    a = analysis.alpha_star(l0, 10)
+    assert cfg.kind == sagms.KINDS["sagms"]
+    assert cfg.alpha_max == pytest.approx(a, rel=1e-12) and cfg.alpha_min == pytest.approx(0.6 * a, rel=1e-12)
+    assert cfg.alpha_max * cfg.eta <= 1.0 and cfg.eta == pytest.approx(1.0 / a, rel=1e-12)
+    cfg2 = sagms.derived_config(l0, 10, ratio=0.5, eta=1.1)
+    assert cfg2.eta == 1.1 and cfg2.alpha_min == pytest.approx(0.5 * a, rel=1e-12)
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    assert sagms.lib().sagms_decode(g._h, None, None, ctypes.byref(cfg), 0, None, None, None, None) == sagms.OK
+    L = sagms.lib()
+    for bad in ((0.0, 10, 0.6, 0.0), (3.0, 1, 0.6, 0.0), (3.0, 10, 0.0, 0.0), (3.0, 10, 1.5, 0.0),
+                (3.0, 10, 0.6, 0.5), (15.0, 2, 0.6, 1.5)):
+        assert L.sagms_derive_gains(*bad, ctypes.byref(sagms.decoder_config())) == sagms.EINVAL
+
+
+def test_fer_ratio_interval_matches_oracle():
+    from oracle import stats as ostats
+    from paper_2605_10433_amd.stats import fer_ratio_interval
+    for f1, n1, f2, n2 in ((500, 10 ** 6, 600, 10 ** 6), (37, 20000, 91, 50000), (1, 10, 9, 10)):
+        got = fer_ratio_interval(f1, n1, f2, n2)
+        ref = ostats.log_ratio_interval(f1, n1, f2, n2)
+        assert got == pytest.approx(ref, rel=1e-12)
+    with pytest.raises(ValueError):
+        fer_ratio_interval(0, 10, 1, 10)

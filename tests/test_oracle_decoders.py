@@ -410,3 +410,42 @@ def test_int6_posteriors_are_exact_sums():
     r = decoders.decode(g, s, llr, DecoderParams(kind="sms", alpha=0.75, lmax=12), "int6", trace=True)
     for rd in r.trace:
         assert ((rd["post"] * 4) == np.round(rd["post"] * 4)).all()
+
+
+def test_grid24():
+    x = np.array([3.5835189, -0.7, 1e-9, -1e-9, 2.0 ** -25, 3 * 2.0 ** -25, 123.456, -0.0], dtype=np.float32)
+    y = decoders.grid24(x)
+    assert y[0] == x[0] and y[6] == x[6]                                   # |x| >= 1: unchanged
+    assert ((y.astype(np.float64) * 2.0 ** 24) == np.round(y.astype(np.float64) * 2.0 ** 24)).all()
+    assert y[2] == 0.0 and y[3] == 0.0 and not np.signbit(y[3]) and not np.signbit(y[7])
+    assert y[4] == 0.0 and y[5] == 2.0 ** -23                              # ties to even
+    assert abs(float(y[1]) - (-0.7)) <= 2.0 ** -25
+
+
+@pytest.mark.parametrize("arith", ["fp16", "int6"])
+def test_check_outputs_need_only_output_rounding(arith):
+    """The message rounding is monotone and keeps signs, so a check update on
+    rounded v2c messages equals: signs of the unrounded messages, exclusive
+    minima of the unrounded magnitudes, rounded, times the gain, rounded.
+    Inputs are on the format's grid before rounding (multiples of 2^-24 for
+    FP16, of 1/4 for INT6: the values the decoder produces), with ties,
+    zeros and magnitudes beyond the format's range."""
+    rng = np.random.default_rng(5)
+    step = 2.0 ** -24 if arith == "fp16" else 0.25
+    for trial in range(300):
+        d = int(rng.integers(2, 12))
+        scale = [1e-6, 1e-3, 1.0, 30.0, 1e5][trial % 5]
+        v = (np.round(rng.normal(0, scale, size=(4, 3, d)) / step) * step).astype(np.float32)
+        v[0, 0, :2] = v[0, 0, 2] if d > 2 else v[0, 0, 0]                 # exact ties
+        v[1, 1, 0] = 0.0
+        v[2, 2, :] = np.abs(v[2, 2, :])
+        s = rng.integers(0, 2, size=(4, 3)).astype(np.uint8)
+        gain = rng.choice([0.3, 0.5, 0.55, 1.0], size=(4, 3)).astype(np.float32)
+        ref = decoders.cn_minsum(decoders.quantize(v, arith), s, gain, arith)
+        mag = np.abs(v)
+        other = ~np.eye(d, dtype=bool)
+        excl = np.where(other, mag[..., None, :], np.inf).min(axis=-1)
+        out = decoders.quantize(gain[..., None] * decoders.quantize(excl, arith), arith)
+        neg = ((v < 0)[..., None, :] & other).sum(axis=-1) + s[..., None]
+        out = np.where(neg & 1, -out, out)
+        assert (out.view(np.uint32) == ref.view(np.uint32)).all(), (trial, arith)
