@@ -276,9 +276,10 @@ def run_serve(args):
                 sagms.gen_errors(g, workloads.SERVE_SEED, workloads.serve_stream(c), ((li + 1) << 28) + f0, nf, p,
                                  buf["ex"], None, buf["synd"])
                 synd[f0:f0 + nf] = buf["synd"].cpu().numpy().view(np.uint64)
-            ehat = np.zeros((max(total, 1), g.words_n), dtype=np.uint64)
-            iters = np.zeros(max(total, 1), dtype=np.int32)
-            conv = np.zeros(max(total, 1), dtype=np.uint8)
+            # written (not just allocated) so that no page is first touched inside the timed replay
+            ehat = np.full((max(total, 1), g.words_n), 0xFF, dtype=np.uint64)
+            iters = np.full(max(total, 1), -1, dtype=np.int32)
+            conv = np.full(max(total, 1), 0xFF, dtype=np.uint8)
             keep += [synd, ehat, iters, conv]
             lo = np.concatenate([[0], np.cumsum(size[sel])[:-1]]).astype(np.int64) if len(sel) else np.zeros(0, np.int64)
             reqs["code"][sel] = c
