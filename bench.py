@@ -38,16 +38,24 @@ OPS_PER_EDGE_UPDATE = 8
 # WRITE_SIZE, KiB per dispatch) and the copy-kernel calibration; used only
 # while the kernel source is unchanged since the counters were taken.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_g63_sagms_p005_traffic.json")
-DECODE_SOURCE = os.path.join(ROOT, "paper_2605_10433_amd", "csrc", "decode.hip")
+DECODE_SOURCES = [os.path.join(ROOT, "paper_2605_10433_amd", "csrc", f) for f in ("decode.hip", "decode_core.h")]
+
+
+def decode_source_sha256():
+    """SHA-256 of the decode kernel's sources (decode.hip, then decode_core.h)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in DECODE_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(frames, p):
     """HBM bytes per decode launch from the committed counter record, or None."""
-    import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = json.load(open(TRAFFIC_FILE))
-    sha = hashlib.sha256(open(DECODE_SOURCE, "rb").read()).hexdigest()
+    sha = decode_source_sha256()
     if rec.get("decode_source_sha256") != sha or rec.get("frames_per_launch") != frames or rec.get("p") != p:
         return None
     return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
@@ -341,7 +349,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--frames", type=int, default=1 << 20)
     ap.add_argument("--p", type=float, default=None, help="noise level (default 0.05; 0.04 for the mix)")
     ap.add_argument("--workload", default="g63", choices=["g63", "mix", "serve"],
@@ -367,11 +375,15 @@ def main():
                          "from the rows of H_Z (ascending check order)")
     ap.add_argument("--frames-per-wave", type=int, default=0, help="decode launch shape (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--source-sha", action="store_true", help="only print the decode sources' SHA-256")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (traffic-counter calibration)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.source_sha:
+        print(decode_source_sha256())
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the decoder is data-parallel over frames and a multi-GPU run "

@@ -91,14 +91,20 @@ __device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c) 
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x78);
 }
 
-// Sign bit of init XOR the signs of x[0..N-1], two inputs per step.
+// init XOR the bit patterns of x[0..N-1], two inputs per step: the sign bit
+// is the parity of the signs; the other bits are not used.
 template <int N>
 __device__ __forceinline__ uint32_t xor_signs(const float (&x)[N], uint32_t init) {
     uint32_t acc = init;
 #pragma unroll
     for (int p = 0; p + 1 < N; p += 2) acc = xor3(acc, bits(x[p]), bits(x[p + 1]));
     if constexpr (N % 2) acc ^= bits(x[N - 1]);
-    return acc & kSign;
+    return acc;
+}
+
+// a | (b & c) in one 3-input bit operation.
+__device__ __forceinline__ uint32_t or_and(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xF8);
 }
 
 // Message formats: FP32; FP16 (every message saturated to +-65504 and
@@ -140,22 +146,22 @@ __device__ __forceinline__ float prior(float x) {
 
 // Check-node update of one check (eq. (ms_cn) scaled per eq. (alphaeff) /
 // (sagms_cn), or eq. (bp4_cn) for BP): v = incoming v2c messages, sb = the
-// original syndrome bit, res = the residual bit (both at the sign position),
+// original syndrome bit at the sign position, unsat = the residual bit,
 // gs / gu = the gains of a satisfied / unsatisfied check.
 template <int DC, bool BP, int MT>
-__device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, uint32_t res, float gs, float gu,
+__device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, bool unsat, float gs, float gu,
                                           float (&c2v)[DC]) {
-    const uint32_t par = xor_signs<DC>(v, sb);
+    const uint32_t par = xor_signs<DC>(v, sb);  // parity in the sign bit only
     if constexpr (BP) {
         float mag[DC];
         bp_magnitudes<DC>(v, mag);
 #pragma unroll
         for (int p = 0; p < DC; ++p) c2v[p] = __uint_as_float(bits(mag[p]) | ((bits(v[p]) ^ par) & kSign));
     } else {
-        const float alpha = res ? gu : gs;
-        float m1 = __builtin_inff(), m2 = __builtin_inff();
+        const float alpha = unsat ? gu : gs;
+        float m1 = fabsf(v[0]), m2 = __builtin_inff();
 #pragma unroll
-        for (int p = 0; p < DC; ++p) {
+        for (int p = 1; p < DC; ++p) {
             float x = fabsf(v[p]);
             m2 = __builtin_amdgcn_fmed3f(m1, x, m2);
             m1 = fminf(m1, x);
@@ -166,11 +172,11 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, uin
         // from folding the select back into one product per edge.
         uint32_t S1, S2;
         if constexpr (MT == SAGMS_MSG_FP32) {
-            S1 = bits(alpha * m1) | par;
-            S2 = bits(alpha * m2) | par;
+            S1 = or_and(bits(alpha * m1), par, kSign);
+            S2 = or_and(bits(alpha * m2), par, kSign);
         } else {
-            S1 = bits(quantize<MT>(alpha * quantize<MT>(m1))) | par;
-            S2 = bits(quantize<MT>(alpha * quantize<MT>(m2))) | par;
+            S1 = or_and(bits(quantize<MT>(alpha * quantize<MT>(m1))), par, kSign);
+            S2 = or_and(bits(quantize<MT>(alpha * quantize<MT>(m2))), par, kSign);
         }
         asm("" : "+v"(S1), "+v"(S2));
 #pragma unroll
@@ -247,7 +253,7 @@ struct WaveDecoder {
         while (true) {
             // top of the round: v2c, hard-decision parity, residual syndrome
             float v[CPL][DC];
-            uint32_t res[CPL];  // residual syndrome bit at the sign position
+            bool unsat[CPL];  // residual syndrome bit: s xor (H e_hat) of the check
             int w = 0;
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
@@ -257,8 +263,8 @@ struct WaveDecoder {
                     pj[p] = lds[caddr[k][p]];
                     v[k][p] = pj[p] - c2v[k][p];  // rounded only through the check output
                 }
-                res[k] = xor_signs<DC>(pj, sb[k]);
-                w += __builtin_popcountll(ballot(res[k] != 0));
+                unsat[k] = (int32_t)xor_signs<DC>(pj, sb[k]) < 0;
+                w += __builtin_popcountll(ballot(unsat[k]));
             }
             if (w == 0) {
                 conv = true;
@@ -278,7 +284,7 @@ struct WaveDecoder {
             }
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
-                cn_update<DC, BP, MT>(v[k], sb[k], res[k], gs, gu, c2v[k]);
+                cn_update<DC, BP, MT>(v[k], sb[k], unsat[k], gs, gu, c2v[k]);
 #pragma unroll
                 for (int p = 0; p < DC; ++p) lds[p * LY::CW + k * 64 + lane] = c2v[k][p];
             }
