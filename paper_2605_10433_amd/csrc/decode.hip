@@ -18,9 +18,14 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
     const int64_t f_begin = wave * a.frames_per_wave;
     if (f_begin >= a.nframes) return;
     const int64_t f_end = min(f_begin + (int64_t)a.frames_per_wave, a.nframes);
-    WaveDecoder<DC, DV, CPL, VPL, BP, MT> d;
+    using WD = WaveDecoder<DC, DV, CPL, VPL, BP, MT>;
+    WD d;
     d.load(a, lds, lane);
-    for (int64_t f = f_begin; f < f_end; ++f) d.frame(a, lds, lane, f);
+    uint64_t word[CPL];
+    uint32_t sb[CPL];
+    WD::load_syndrome(a, f_begin, word);
+    WD::syndrome_bits(a, lane, word, sb);
+    for (int64_t f = f_begin; f < f_end; ++f) d.frame(a, lds, lane, f, sb, f + 1 < f_end ? f + 1 : f);
 }
 
 // Waves per block: up to kWavesPerBlock, as many as fit in 64 KiB of LDS.

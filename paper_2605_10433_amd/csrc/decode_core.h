@@ -225,16 +225,27 @@ struct WaveDecoder {
         }
     }
 
-    // Decodes frame f and writes its outputs.
-    __device__ __forceinline__ void frame(const DecodeArgs& a, float* lds, int lane, int64_t f) {
-        // original syndrome bit of each owned check, at the sign position
-        // (checks beyond m read as 0; their rows hold only the +inf padding)
-        uint32_t sb[CPL];
+    // Original syndrome bits of frame f for the lane's checks, at the sign
+    // position (checks beyond m read as 0; their rows hold only the +inf
+    // padding).
+    __device__ __forceinline__ static void load_syndrome(const DecodeArgs& a, int64_t f, uint64_t (&word)[CPL]) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            uint64_t word = k < a.wm ? a.synd[f * a.wm + k] : 0ull;
-            sb[k] = (k * 64 + lane < a.m) ? (uint32_t)((word >> lane) & 1ull) << 31 : 0u;
-        }
+        for (int k = 0; k < CPL; ++k) word[k] = k < a.wm ? a.synd[f * a.wm + k] : 0ull;
+    }
+    __device__ __forceinline__ static void syndrome_bits(const DecodeArgs& a, int lane, const uint64_t (&word)[CPL],
+                                                         uint32_t (&sb)[CPL]) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+            sb[k] = (k * 64 + lane < a.m) ? (uint32_t)((word[k] >> lane) & 1ull) << 31 : 0u;
+    }
+
+    // Decodes frame f, whose syndrome bits are sb, and writes its outputs.
+    // The syndrome of frame f_next is loaded when the frame starts and left
+    // in sb when its rounds are done, so the load latency hides behind them.
+    __device__ __forceinline__ void frame(const DecodeArgs& a, float* lds, int lane, int64_t f, uint32_t (&sb)[CPL],
+                                          int64_t f_next) {
+        uint64_t next_word[CPL];
+        load_syndrome(a, f_next, next_word);
         float post[VPL];
 #pragma unroll
         for (int k = 0; k < VPL; ++k) {
@@ -301,6 +312,11 @@ struct WaveDecoder {
             wave_lds_sync();
         }
 
+        syndrome_bits(a, lane, next_word, sb);
+        // take the prefetched bits before the output stores are issued: a
+        // wait placed after them would also wait for the stores
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) asm volatile("" ::"v"(sb[k]));
         // outputs: hard decisions, round count, convergence flag
         uint64_t mine = 0;
 #pragma unroll

@@ -51,12 +51,17 @@ __device__ __forceinline__ int64_t run_segment(const MixedArgs& m, int s, int64_
                                                int lane) {
     const DecodeArgs a = m.segs[s].a;  // private copy: the output stores cannot alias it
     const int64_t tb = s == 0 ? 0 : m.tile_end[s - 1], te = m.tile_end[s];
-    WaveDecoder<DC, DV, CPL, VPL, BP, MT> d;
+    using WD = WaveDecoder<DC, DV, CPL, VPL, BP, MT>;
+    WD d;
     d.load(a, lds, lane);
     do {
         const int64_t f0 = (t - tb) * m.tile_frames;
         const int64_t f1 = min(f0 + (int64_t)m.tile_frames, a.nframes);
-        for (int64_t f = f0; f < f1; ++f) d.frame(a, lds, lane, f);
+        uint64_t word[CPL];
+        uint32_t sb[CPL];
+        WD::load_syndrome(a, f0, word);
+        WD::syndrome_bits(a, lane, word, sb);
+        for (int64_t f = f0; f < f1; ++f) d.frame(a, lds, lane, f, sb, f + 1 < f1 ? f + 1 : f);
         t = q.next(m, lane);
     } while (t >= tb && t < te);
     return t;
