@@ -73,9 +73,10 @@ def copy_calibration(nbytes=1 << 30, reps=4):
     print(json.dumps({"copy_bytes_per_dispatch": nbytes, "dispatches": reps}), flush=True)
 
 
-def cpu_baseline(p, lmax, params, frames=1 << 13):
-    """The oracle (FP64, NumPy, one thread) on a bounded sample of the same
-    workload: frames 0 .. frames-1 of the same stream."""
+def oracle_frames(p, lmax, params, frame0, frames):
+    """The oracle (FP64, NumPy, one BLAS thread) over frames frame0 ..
+    frame0 + frames - 1 of the bench workload: sampling, syndromes, SAGMS
+    decoding and the judge.  Returns (seconds, failures)."""
     from threadpoolctl import threadpool_limits
 
     import workloads
@@ -88,14 +89,42 @@ def cpu_baseline(p, lmax, params, frames=1 << 13):
     prm = decoders.DecoderParams(kind="sagms", lmax=lmax, **params)
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        ex, _ = channel.sample_paulis(workloads.SWEEP_SEED, workloads.stream_of(p), 0, frames, 2 * l, p)
+        ex, _ = channel.sample_paulis(workloads.SWEEP_SEED, workloads.stream_of(p), frame0, frames, 2 * l, p)
         s = channel.syndrome(hz, ex)
         r = decoders.decode(tg, s, llr, prm, "fp64")
-        judge.judge_logical(lz, ex, r.ehat, r.converged)
-        dt = time.perf_counter() - t0
-    return {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": "%d frames (0..%d) of the same workload, FP64 oracle: sampling + syndromes + SAGMS decode "
-                      "+ judge, %.1f s" % (frames, frames - 1, dt)}
+        fail = judge.judge_logical(lz, ex, r.ehat, r.converged)
+        return time.perf_counter() - t0, int(fail.sum())
+
+
+def _oracle_worker(args):
+    return oracle_frames(*args)
+
+
+def cpu_baseline(p, lmax, params, frames=1 << 13, procs=None):
+    """The oracle on a bounded sample of the same workload: frames
+    0 .. frames-1 on one core, then (procs > 1) the same number of frames per
+    process on a pool of `procs` processes (started by spawn, no GPU state),
+    frame ranges split by Philox counter, timed from the first task to the
+    last result."""
+    dt, _ = oracle_frames(p, lmax, params, 0, frames)
+    out = {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+           "sample": "%d frames (0..%d) of the same workload, FP64 oracle: sampling + syndromes + SAGMS decode "
+                     "+ judge, %.1f s on one core" % (frames, frames - 1, dt)}
+    if procs is None:
+        procs = min(16, os.cpu_count() or 1)
+    if procs > 1:
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(procs) as pool:
+            pool.map(_oracle_worker, [(p, lmax, params, 0, 64)] * procs)  # imports and first calls
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_worker, [(p, lmax, params, frames * (i + 1), frames) for i in range(procs)])
+            wall = time.perf_counter() - t0
+        out["all_cores"] = {"value": frames * procs / wall, "unit": "frames/s", "cores": procs,
+                            "host_cpu_count": os.cpu_count(),
+                            "sample": "%d processes x %d frames (frames %d..%d), %.1f s wall" % (
+                                procs, frames, frames, frames * (procs + 1) - 1, wall)}
+    return out
 
 
 def gb_dense(l, a, b):
