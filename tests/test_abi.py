@@ -280,3 +280,22 @@ def test_fer_ratio_interval_matches_oracle():
         assert got == pytest.approx(ref, rel=1e-12)
     with pytest.raises(ValueError):
         fer_ratio_interval(0, 10, 1, 10)
+
+
+def test_codes_beyond_every_decode_shape_are_refused():
+    """A graph no compiled decode shape fits (n > 1024, or a check degree
+    above 16) builds, but decoding, batching and serving it are refused with
+    SAGMS_EUNSUPPORTED before any device work."""
+    big = sagms.Graph.gb(600, [0, 1, 5, 11, 40], [0, 2, 9, 30, 77])          # n = 1200
+    dense = np.zeros((4, 40), dtype=np.uint8)
+    dense[0, :20] = 1                                                     # a check of degree 20
+    dense[1, 20:] = 1
+    dense[2, ::2] = 1
+    dense[3, 1::2] = 1
+    wide = sagms.Graph.from_dense(dense)
+    for g in (big, wide):
+        assert sagms.lib().sagms_decode(g._h, None, None, ctypes.byref(sagms.decoder_config("ms")), 4,
+                                        None, None, None, None) == sagms.EUNSUPPORTED
+        assert "no decode kernel" in sagms.lib().sagms_last_error().decode()
+        assert _create_rc(_segments([g], [4]), 1, sagms.decoder_config("sagms")) == sagms.EUNSUPPORTED
+    assert (big.n, big.dc_max) == (1200, 10) and wide.dc_max == 20
