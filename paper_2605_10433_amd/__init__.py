@@ -19,7 +19,9 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsagms.so")
+# SAGMS_LIBRARY may name another build of the same library (a sanitizer
+# build of the host code, for instance); there is no other fallback.
+LIB_PATH = os.environ.get("SAGMS_LIBRARY") or os.path.join(_HERE, "libsagms.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sagms.h")
 
 OK, EINVAL, ENOMEM, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4

@@ -92,8 +92,8 @@ struct Batch {
 };
 
 void drop_graph(Batch* b) {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
 }
@@ -157,7 +157,7 @@ int check_device(const Batch* b) {
 
 void destroy(Batch* b) {
     drop_graph(b);
-    if (b->d_queues) hipFree(b->d_queues);
+    if (b->d_queues) (void)hipFree(b->d_queues);
     delete b;
 }
 
@@ -282,22 +282,22 @@ int sagms_batch_instantiate(sagms_batch bh) {
     SAGMS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         return hip_fail(e, "hipStreamBeginCapture");
     }
     rc = enqueue(b, cs);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (rc) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return rc;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         return hip_fail(e, "hipGraphInstantiate");
     }
     b->graph = graph;
@@ -373,8 +373,8 @@ int sagms_batch_tune(sagms_batch bh, void* stream, int32_t reps, sagms_tune_resu
             best_plan = p;
         }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (he == hipSuccess && !rc) he = hipStreamSynchronize(st);
     if (he != hipSuccess || rc) {
         b->plan = saved;

@@ -80,17 +80,17 @@ struct Server {
 
 void destroy(Server* s) {
     for (Slot& x : s->slots) {
-        if (x.st) hipStreamSynchronize(x.st);
-        if (x.done) hipEventDestroy(x.done);
-        if (x.st) hipStreamDestroy(x.st);
-        if (x.h_in) hipHostFree(x.h_in);
-        if (x.h_out) hipHostFree(x.h_out);
-        if (x.d_in) hipFree(x.d_in);
-        if (x.d_out) hipFree(x.d_out);
-        if (x.d_queues) hipFree(x.d_queues);
+        if (x.st) (void)hipStreamSynchronize(x.st);
+        if (x.done) (void)hipEventDestroy(x.done);
+        if (x.st) (void)hipStreamDestroy(x.st);
+        if (x.h_in) (void)hipHostFree(x.h_in);
+        if (x.h_out) (void)hipHostFree(x.h_out);
+        if (x.d_in) (void)hipFree(x.d_in);
+        if (x.d_out) (void)hipFree(x.d_out);
+        if (x.d_queues) (void)hipFree(x.d_queues);
     }
     for (Code& c : s->codes)
-        if (c.llr0) hipFree(c.llr0);
+        if (c.llr0) (void)hipFree(c.llr0);
     delete s;
 }
 
