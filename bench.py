@@ -6,7 +6,9 @@ frames: depolarizing errors + syndromes (sagms_gen_errors), SAGMS decoding
 l = 63 GB code ([[126,28]], H_Z with m = 63, d_c = 10, d_v = 5, 630 edges),
 p = 0.05, 2^20 frames per step, SAGMS (alpha_min, alpha_max, eta) =
 (0.30, 0.50, 1.10), l_max = 100 with per-frame early exit, FP32 messages.
-Step s decodes frames [s * 2^20, (s + 1) * 2^20) of Philox stream 4.
+Step s decodes frames [s * 2^20, (s + 1) * 2^20) of Philox stream 4.  The
+sampler of step s + 1 runs on a second stream while step s decodes (two
+frame buffers; --no-pipeline runs each step in one stream).
 
 Prints one JSON line (see the project documentation for every field).
 """
@@ -186,7 +188,9 @@ def run_mix(args):
             sagms.judge(sg["graph"], sg["ex"], sg["ehat"], sg["converged"], sg["iters"], counters[i])
 
     for s in range(args.warmup):
-        step(args.steps + s)
+        if side is not None and s == 0:
+            sample(args.steps)
+        step(args.steps + s, next_s=args.steps + s + 1 if s + 1 < args.warmup else None)
     torch.cuda.synchronize()
     counters.zero_()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -194,8 +198,11 @@ def run_mix(args):
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     t_start.record(stream)
+    if side is not None:  # the first sampling is part of the timed region
+        side.wait_event(t_start)
+        sample(0)
     for s in range(args.steps):
-        step(s, events[s])
+        step(s, events[s], next_s=s + 1 if s + 1 < args.steps else None)
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -403,6 +410,9 @@ def main():
                     help="build the code from its polynomials (posteriors summed in polynomial-term order) or "
                          "from the rows of H_Z (ascending check order)")
     ap.add_argument("--frames-per-wave", type=int, default=0, help="decode launch shape (0 = library default)")
+    ap.add_argument("--no-pipeline", dest="pipeline", action="store_false",
+                    help="run sampling, decoding and the judge of each step in one stream (by default the sampler "
+                         "of step s + 1 runs on a second stream while step s decodes, on two frame buffers)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--source-sha", action="store_true", help="only print the decode sources' SHA-256")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -443,24 +453,51 @@ def main():
         kernel = "decode_kernel<10,5,1,2,%s>" % ("true" if args.decoder == "bp" else "false")
     nf, p = args.frames, args.p
     stream_id = workloads.stream_of(p) if p in workloads.P_GRID else 0
-    buf = sagms.frame_buffers(g, nf, device=dev)
+    bufs = [sagms.frame_buffers(g, nf, device=dev) for _ in range(2 if args.pipeline else 1)]
     llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
     cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, frames_per_wave=args.frames_per_wave,
                                **workloads.SAGMS_PARAMS)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
+    # --pipeline: the sampler of step s + 1 runs on a second stream while step
+    # s decodes, on the other of two frame buffers; a step's decode waits for
+    # its own samples, a buffer's next sampling waits for its judge.
+    side = torch.cuda.Stream(device=dev) if args.pipeline else None
+    sampled = [torch.cuda.Event() for _ in bufs]
+    judged = [torch.cuda.Event() for _ in bufs]
 
-    def step(s, ev=None):
-        sagms.gen_errors(g, workloads.SWEEP_SEED, stream_id, s * nf, nf, p, buf["ex"], buf["ez"], buf["synd"])
+    def sample(s):
+        b = s % len(bufs)
+        if side is None:
+            sagms.gen_errors(g, workloads.SWEEP_SEED, stream_id, s * nf, nf, p, bufs[b]["ex"], bufs[b]["ez"],
+                             bufs[b]["synd"])
+            return
+        side.wait_event(judged[b])
+        sagms.gen_errors(g, workloads.SWEEP_SEED, stream_id, s * nf, nf, p, bufs[b]["ex"], bufs[b]["ez"],
+                         bufs[b]["synd"], stream=side)
+        sampled[b].record(side)
+
+    def step(s, ev=None, next_s=None):
+        b = s % len(bufs)
+        buf = bufs[b]
+        if side is None:
+            sample(s)
+        else:
+            stream.wait_event(sampled[b])
+            if next_s is not None:
+                sample(next_s)
         if ev is not None:
             ev[0].record(stream)
         sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
         if ev is not None:
             ev[1].record(stream)
         sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters)
+        judged[b].record(stream)
 
     for s in range(args.warmup):
-        step(args.steps + s)
+        if side is not None and s == 0:
+            sample(args.steps)
+        step(args.steps + s, next_s=args.steps + s + 1 if s + 1 < args.warmup else None)
     torch.cuda.synchronize()
     counters.zero_()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -468,8 +505,11 @@ def main():
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     t_start.record(stream)
+    if side is not None:  # the first sampling is part of the timed region
+        side.wait_event(t_start)
+        sample(0)
     for s in range(args.steps):
-        step(s, events[s])
+        step(s, events[s], next_s=s + 1 if s + 1 < args.steps else None)
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -479,7 +519,20 @@ def main():
     frames = nf * args.steps
     sum_iters = int(c[1])
     edge_updates = sum_iters * g.n_edges
-    it_last = buf["iters"].float()
+    last = bufs[(args.steps - 1) % len(bufs)]
+    it_last = last["iters"].float()
+    # the decode kernel alone (no overlapped sampling): ten more launches, back
+    # to back on the last step's syndromes outside the timed region; the
+    # median of the last five (the clock drops while the host synchronizes)
+    iso_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for e0, e1 in iso_ev:
+        e0.record(stream)
+        sagms.decode(g, last["synd"], llr, cfg, last["ehat"], last["iters"], last["converged"])
+        e1.record(stream)
+    torch.cuda.synchronize()
+    iso_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in iso_ev[5:]]))
+    iso_ops = OPS_PER_EDGE_UPDATE * int(last["iters"].long().sum().item()) * g.n_edges
+    iso_achieved = iso_ops / (iso_ms * 1e-3) / 1e12
     mean_dec_ms = float(np.mean(dec_ms))
     ops_per_launch = OPS_PER_EDGE_UPDATE * edge_updates / args.steps
     achieved = ops_per_launch / (mean_dec_ms * 1e-3) / 1e12
@@ -502,7 +555,8 @@ def main():
         "config": {"workload": "GB l=63 [[126,28]] (H_Z: m=63, d_c=10, d_v=5, E=630), code-capacity depolarizing "
                                "p=%g, %d Philox frames/step, %s l_max=%d early exit, flooding, FP32 messages"
                                % (p, nf, args.decoder.upper(), args.lmax),
-                   "code": "G63", "graph": args.graph, "frames_per_wave": args.frames_per_wave, "p": p, "frames_per_step": nf, "decoder": args.decoder, "lmax": args.lmax},
+                   "code": "G63", "graph": args.graph, "frames_per_wave": args.frames_per_wave, "p": p, "frames_per_step": nf, "decoder": args.decoder, "lmax": args.lmax,
+                   "pipeline": bool(args.pipeline)},
         "edge_updates_per_s": edge_updates / (total_ms * 1e-3),
         "decode_ms_per_step": mean_dec_ms,
         "decode_frames_per_s": nf / (mean_dec_ms * 1e-3),
@@ -515,7 +569,10 @@ def main():
                      "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": measured_traffic(nf, p) if args.graph == "gb" and args.decoder == "sagms" else None,
                      "kernel": kernel,
-                     "ops_per_edge_update": OPS_PER_EDGE_UPDATE},
+                     "ops_per_edge_update": OPS_PER_EDGE_UPDATE,
+                     "note": "decode launch time inside the pipelined steps (the next step's sampler shares the GPU)"
+                             if args.pipeline else "decode launch time, one stream",
+                     "isolated": {"decode_ms": iso_ms, "achieved": iso_achieved, "frac": iso_achieved / VALU_PEAK_TOPS}},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.lmax, workloads.SAGMS_PARAMS)
