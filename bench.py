@@ -151,41 +151,70 @@ def run_mix(args):
     p = args.p if args.p is not None else workloads.MIX_P
     cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, precision=args.precision,
                                **workloads.SAGMS_PARAMS)
-    segs = []
-    for i, (name, nf) in enumerate(zip(workloads.MIX_CODES, workloads.MIX_FRAMES)):
-        g = sagms.Graph.gb(*workloads.code(name))
-        buf = sagms.frame_buffers(g, nf, device=dev, with_ez=False)
-        segs.append(dict(graph=g, name=name, nf=nf, synd=buf["synd"], ex=buf["ex"], ehat=buf["ehat"],
-                         iters=buf["iters"], converged=buf["converged"], stream_id=workloads.mix_stream(i, p),
-                         llr0=torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)))
-    batch = sagms.Batch(segs, cfg)
+    # --pipeline: two frame-buffer sets, each bound to its own batch, and the
+    # samplers of step s + 1 run on a second stream while step s decodes.  Off
+    # by default here: the persistent decode keeps every CU busy to its last
+    # tile, so the ALU-bound sampler beside it only takes cycles from it.
+    nsets = 2 if args.pipeline else 1
+    sets = []
+    for _ in range(nsets):
+        segs = []
+        for i, (name, nf) in enumerate(zip(workloads.MIX_CODES, workloads.MIX_FRAMES)):
+            g = sagms.Graph.gb(*workloads.code(name))
+            buf = sagms.frame_buffers(g, nf, device=dev, with_ez=False)
+            segs.append(dict(graph=g, name=name, nf=nf, synd=buf["synd"], ex=buf["ex"], ehat=buf["ehat"],
+                             iters=buf["iters"], converged=buf["converged"], stream_id=workloads.mix_stream(i, p),
+                             llr0=torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)))
+        sets.append(segs)
+    segs = sets[0]
+    batches = [sagms.Batch(st, cfg) for st in sets]
+    batch = batches[0]
     counters = torch.zeros((len(segs), 2), dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream(device=dev) if args.pipeline else None
+    sampled = [torch.cuda.Event() for _ in sets]
+    judged = [torch.cuda.Event() for _ in sets]
 
-    def fill(s):
-        for sg in segs:
+    def sample(s):
+        b = s % nsets
+        if side is not None:
+            side.wait_event(judged[b])
+        for sg in sets[b]:
             sagms.gen_errors(sg["graph"], workloads.MIX_SEED, sg["stream_id"], s * sg["nf"], sg["nf"], p, sg["ex"],
-                             None, sg["synd"])
+                             None, sg["synd"], stream=side)
+        if side is not None:
+            sampled[b].record(side)
 
     tune_log = None
     if args.tune:
-        fill(args.steps + args.warmup)
+        sample(2 * (args.steps + args.warmup))  # into the first set, which the tuner runs on
+        torch.cuda.synchronize()
         best, results = batch.tune(reps=3)
         tune_log = sorted(results, key=lambda r: r[1])
     elif args.plan:
         batch.set_plan(sagms.plan(**json.loads(args.plan)))
+    for other in batches[1:]:
+        other.set_plan(batch.get_plan())
     if args.graph_launch:
-        batch.instantiate()
+        for bt in batches:
+            bt.instantiate()
 
-    def step(s, ev=None):
-        fill(s)
+    def step(s, ev=None, next_s=None):
+        b = s % nsets
+        if side is None:
+            sample(s)
+        else:
+            stream.wait_event(sampled[b])
+            if next_s is not None:
+                sample(next_s)
         if ev is not None:
             ev[0].record(stream)
-        batch.run()
+        batches[b].run()
         if ev is not None:
             ev[1].record(stream)
-        for i, sg in enumerate(segs):
+        for i, sg in enumerate(sets[b]):
             sagms.judge(sg["graph"], sg["ex"], sg["ehat"], sg["converged"], sg["iters"], counters[i])
+        judged[b].record(stream)
 
     for s in range(args.warmup):
         if side is not None and s == 0:
@@ -239,7 +268,8 @@ def run_mix(args):
                                   frames_step, p, args.decoder.upper(), args.lmax, args.precision.upper()),
                    "codes": workloads.MIX_CODES, "frames_per_step": workloads.MIX_FRAMES, "p": p,
                    "decoder": args.decoder, "lmax": args.lmax, "precision": args.precision, "plan": plan,
-                   "graph_launch": bool(args.graph_launch), "tuned": bool(args.tune)},
+                   "graph_launch": bool(args.graph_launch), "tuned": bool(args.tune),
+                   "pipeline": bool(args.pipeline)},
         "decode_ms_per_step": dec_ms,
         "decode_frames_per_s": frames_step / (dec_ms * 1e-3),
         "per_code": per_code,
@@ -410,14 +440,19 @@ def main():
                     help="build the code from its polynomials (posteriors summed in polynomial-term order) or "
                          "from the rows of H_Z (ascending check order)")
     ap.add_argument("--frames-per-wave", type=int, default=0, help="decode launch shape (0 = library default)")
+    ap.add_argument("--pipeline", dest="pipeline", action="store_true", default=None,
+                    help="run the sampler of step s + 1 on a second stream while step s decodes, on two sets of "
+                         "frame buffers (default for the single-code workload)")
     ap.add_argument("--no-pipeline", dest="pipeline", action="store_false",
-                    help="run sampling, decoding and the judge of each step in one stream (by default the sampler "
-                         "of step s + 1 runs on a second stream while step s decodes, on two frame buffers)")
+                    help="run sampling, decoding and the judge of each step in one stream (default for the "
+                         "mixed-code workload, whose persistent decode already fills the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--source-sha", action="store_true", help="only print the decode sources' SHA-256")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (traffic-counter calibration)")
     args = ap.parse_args()
+    if args.pipeline is None:
+        args.pipeline = args.workload == "g63"
     if args.copy_calibration:
         copy_calibration()
         return
