@@ -75,10 +75,11 @@ def copy_calibration(nbytes=1 << 30, reps=4):
     print(json.dumps({"copy_bytes_per_dispatch": nbytes, "dispatches": reps}), flush=True)
 
 
-def oracle_frames(p, lmax, params, frame0, frames):
+def oracle_frames(p, lmax, params, frame0, frames, kind="sagms"):
     """The oracle (FP64, NumPy, one BLAS thread) over frames frame0 ..
-    frame0 + frames - 1 of the bench workload: sampling, syndromes, SAGMS
-    decoding and the judge.  Returns (seconds, failures)."""
+    frame0 + frames - 1 of the bench workload: sampling, syndromes, decoding
+    and the judge.  Returns (seconds, failures, seconds of the decode alone,
+    sum of rounds)."""
     from threadpoolctl import threadpool_limits
 
     import workloads
@@ -88,14 +89,16 @@ def oracle_frames(p, lmax, params, frame0, frames):
     tg = decoders.TannerGraph(hz, codes.gb_var_checks(l, a, b))
     lz = codes.logical_basis(hz, hx)
     llr = np.full(2 * l, channel.prior_llr(p))
-    prm = decoders.DecoderParams(kind="sagms", lmax=lmax, **params)
+    prm = decoders.DecoderParams(kind=kind, lmax=lmax, **params)
     with threadpool_limits(1):
         t0 = time.perf_counter()
         ex, _ = channel.sample_paulis(workloads.SWEEP_SEED, workloads.stream_of(p), frame0, frames, 2 * l, p)
         s = channel.syndrome(hz, ex)
+        t1 = time.perf_counter()
         r = decoders.decode(tg, s, llr, prm, "fp64")
+        t2 = time.perf_counter()
         fail = judge.judge_logical(lz, ex, r.ehat, r.converged)
-        return time.perf_counter() - t0, int(fail.sum())
+        return time.perf_counter() - t0, int(fail.sum()), t2 - t1, int(np.sum(r.iters))
 
 
 def _oracle_worker(args):
@@ -108,7 +111,7 @@ def cpu_baseline(p, lmax, params, frames=1 << 13, procs=None):
     process on a pool of `procs` processes (started by spawn, no GPU state),
     frame ranges split by Philox counter, timed from the first task to the
     last result."""
-    dt, _ = oracle_frames(p, lmax, params, 0, frames)
+    dt = oracle_frames(p, lmax, params, 0, frames)[0]
     out = {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
            "sample": "%d frames (0..%d) of the same workload, FP64 oracle: sampling + syndromes + SAGMS decode "
                      "+ judge, %.1f s on one core" % (frames, frames - 1, dt)}
@@ -127,6 +130,37 @@ def cpu_baseline(p, lmax, params, frames=1 << 13, procs=None):
                             "sample": "%d processes x %d frames (frames %d..%d), %.1f s wall" % (
                                 procs, frames, frames, frames * (procs + 1) - 1, wall)}
     return out
+
+
+def cpu_table(p, lmax, frames=1 << 16, procs=None):
+    """Oracle timing over 2^16 frames of the bench workload for MS, SMS
+    (alpha = 0.75) and SAGMS: one core, then a pool of `procs` processes
+    (frame ranges split by Philox counter); the whole path and the decode
+    alone, in frames/s and edge-updates/s (630 edges per round)."""
+    import multiprocessing as mp
+    import workloads
+    if procs is None:
+        procs = min(16, os.cpu_count() or 1)
+    rows = []
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs) as pool:
+        pool.map(_oracle_worker, [(p, lmax, {}, 0, 64, "ms")] * procs)
+        for kind, params in (("ms", {}), ("sms", dict(alpha=0.75)), ("sagms", workloads.SAGMS_PARAMS)):
+            dt, fails, dec, isum = oracle_frames(p, lmax, params, 0, frames, kind)
+            per = frames // procs
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_worker, [(p, lmax, params, i * per, per, kind) for i in range(procs)])
+            wall = time.perf_counter() - t0
+            dec_all = max(r[2] for r in res)
+            row = {"decoder": kind, "frames": frames, "failures": fails, "mean_iters": isum / frames,
+                   "one_core": {"frames_per_s": frames / dt, "decode_frames_per_s": frames / dec,
+                                "edge_updates_per_s": isum * 630 / dec, "seconds": dt},
+                   "all_cores": {"cores": procs, "frames_per_s": per * procs / wall,
+                                 "decode_frames_per_s_slowest_process": per * procs / dec_all,
+                                 "edge_updates_per_s": sum(r[3] for r in res) * 630 / dec_all, "seconds": wall}}
+            print(json.dumps(row), flush=True)
+            rows.append(row)
+    return rows
 
 
 def gb_dense(l, a, b):
@@ -447,6 +481,8 @@ def main():
                     help="run sampling, decoding and the judge of each step in one stream (default for the "
                          "mixed-code workload, whose persistent decode already fills the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the oracle (MS, SMS 0.75, SAGMS; 2^16 frames; one core and all cores)")
     ap.add_argument("--source-sha", action="store_true", help="only print the decode sources' SHA-256")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (traffic-counter calibration)")
@@ -455,6 +491,10 @@ def main():
         args.pipeline = args.workload == "g63"
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.cpu_table:
+        print(json.dumps({"host_cpu_count": os.cpu_count()}), flush=True)
+        cpu_table(args.p if args.p is not None else 0.05, args.lmax)
         return
     if args.source_sha:
         print(decode_source_sha256())
