@@ -40,11 +40,13 @@ OPS_PER_EDGE_UPDATE = 8
 # WRITE_SIZE, KiB per dispatch) and the copy-kernel calibration; used only
 # while the kernel source is unchanged since the counters were taken.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_g63_sagms_p005_traffic.json")
-DECODE_SOURCES = [os.path.join(ROOT, "paper_2605_10433_amd", "csrc", f) for f in ("decode.hip", "decode_core.h")]
+DECODE_SOURCES = [os.path.join(ROOT, "paper_2605_10433_amd", "csrc", f)
+                  for f in ("decode.hip", "decode_core.h", "schedule.h")]
 
 
 def decode_source_sha256():
-    """SHA-256 of the decode kernel's sources (decode.hip, then decode_core.h)."""
+    """SHA-256 of the decode kernel's sources (decode.hip, decode_core.h,
+    schedule.h, in that order)."""
     import hashlib
     h = hashlib.sha256()
     for f in DECODE_SOURCES:

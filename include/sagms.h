@@ -88,8 +88,12 @@ typedef struct {
     double alpha_max;
     double eta;
     int32_t frames_per_wave; /* launch shape: frames decoded one after the other by
-                                one wavefront (0 = library default, else 1..1024);
-                                results do not depend on it */
+                                one wavefront.  1..1024: that many for every
+                                wavefront.  0 (library default): a tapered
+                                launch, 16 per wavefront, with the frames at
+                                the end of the batch in runs of 8, 4, 2 and 1
+                                so that the last wavefronts finish together.
+                                Results do not depend on it */
     int32_t reserved;        /* must be 0 */
 } sagms_decoder_cfg;
 

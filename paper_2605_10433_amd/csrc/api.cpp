@@ -68,7 +68,7 @@ DecodeArgs decode_args(const Graph* g, const DeviceTables* t, const float* gains
     a.wm = g->wm;
     a.wn = g->wn;
     a.lmax = lmax;
-    a.frames_per_wave = frames_per_wave > 0 ? frames_per_wave : kDecodeFramesPerWave;
+    a.frames_per_wave = frames_per_wave;  // 0: the decode launcher's tapered schedule
     a.L = g->layout;
     return a;
 }

@@ -187,7 +187,7 @@ int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_deco
     b->cfg = *cfg;
     b->mt = cfg->msg_precision;
     b->nseg = nseg;
-    b->plan = sagms_plan{SAGMS_PLAN_SINGLE, kDecodeFramesPerWave, 4, 0, 0, 0};
+    b->plan = sagms_plan{SAGMS_PLAN_SINGLE, kMixedTileFrames, 4, 0, 0, 0};
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e != hipSuccess) {

@@ -1,23 +1,36 @@
-// Decode kernel with a static frame assignment: wave w of the grid decodes
-// frames [w * frames_per_wave, (w + 1) * frames_per_wave).  The per-frame
-// algorithm (Algorithm 1 of the paper) is in decode_core.h.
+// Decode kernel with a static frame assignment (schedule.h): each wave
+// decodes a run of consecutive frames.  The default launch tapers: most
+// frames go in runs of kDecodeFramesPerWave, which amortise a wave's set-up,
+// and the last ones in runs of halving length, so that the waves still
+// running after the whole grid has been dispatched hold little work.  The
+// per-frame algorithm (Algorithm 1 of the paper) is in decode_core.h.
+#include <mutex>
+#include <unordered_map>
+
 #include "decode_core.h"
+#include "schedule.h"
 
 namespace sagms {
 
 constexpr int kWavesPerBlock = 4;
+constexpr int kTaperLevels = 2;  // waves per tail level of the tapered schedule, in resident waves
 
 template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
-__global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs a) {
+__global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs a, WaveSchedule ws) {
     using LY = Lay<DC, CPL, VPL>;
     extern __shared__ float lds_all[];
     const int lane = threadIdx.x & 63;
+    // not made wave-uniform: with a uniform wave index the compiler loads the
+    // syndromes with scalar loads, which fetched twice their bytes from HBM
     const int wib = threadIdx.x >> 6;
     float* lds = lds_all + wib * LY::WORDS;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
-    const int64_t f_begin = wave * a.frames_per_wave;
-    if (f_begin >= a.nframes) return;
-    const int64_t f_end = min(f_begin + (int64_t)a.frames_per_wave, a.nframes);
+    if (wave >= ws.wave0[ws.levels]) return;
+    int k = 0;
+    while (k + 1 < ws.levels && wave >= ws.wave0[k + 1]) ++k;
+    const int64_t f_begin = ws.frame0[k] + (wave - ws.wave0[k]) * ws.chunk[k];
+    const int64_t f_end = min(f_begin + (int64_t)ws.chunk[k], ws.frame0[k + 1]);
+    if (f_begin >= f_end) return;
     using WD = WaveDecoder<DC, DV, CPL, VPL, BP, MT>;
     WD d;
     d.load(a, lds, lane);
@@ -35,8 +48,49 @@ static int waves_per_block(const DecodeLayout& L) {
 }
 
 template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
-static void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const DecodeArgs& a) {
-    hipLaunchKernelGGL((decode_kernel<DC, DV, CPL, VPL, BP, MT>), grid, block, lds, st, a);
+static void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const DecodeArgs& a, const WaveSchedule& ws) {
+    hipLaunchKernelGGL((decode_kernel<DC, DV, CPL, VPL, BP, MT>), grid, block, lds, st, a, ws);
+}
+
+// Waves of one kernel resident on the current device at once (occupancy of
+// registers and LDS times compute units), queried once per kernel and device.
+static int resident_waves(const void* kernel, int wpb, size_t lds, int64_t* out) {
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, int64_t> cache;
+    int dev = 0;
+    SAGMS_HIP(hipGetDevice(&dev));
+    const uint64_t key = reinterpret_cast<uintptr_t>(kernel) * 64 + (uint64_t)dev;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *out = it->second;
+            return SAGMS_OK;
+        }
+    }
+    int blocks = 0, cus = 0;
+    SAGMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, 64 * wpb, lds));
+    SAGMS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t r = std::max<int64_t>(1, (int64_t)blocks * wpb * cus);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = r;
+    *out = r;
+    return SAGMS_OK;
+}
+
+template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
+static int launch_kernel(const DecodeArgs& a, int wpb, size_t lds, hipStream_t st) {
+    int64_t resident = 0;
+    if (a.frames_per_wave == 0) {
+        const int rc = resident_waves(reinterpret_cast<const void*>(&decode_kernel<DC, DV, CPL, VPL, BP, MT>), wpb,
+                                      lds, &resident);
+        if (rc) return rc;
+    }
+    const WaveSchedule ws = make_schedule(a.nframes, a.frames_per_wave, resident * kTaperLevels, kDecodeFramesPerWave);
+    const int64_t blocks = (ws.wave0[ws.levels] + wpb - 1) / wpb;
+    if (blocks > 0x7fffffff) return fail(SAGMS_EINVAL, "too many frames for one launch");
+    launch_one<DC, DV, CPL, VPL, BP, MT>(dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a, ws);
+    return SAGMS_OK;
 }
 
 template <int DC, int DV, int CPL, int VPL>
@@ -47,19 +101,17 @@ static int launch_shape(bool bp, int mt, const DecodeArgs& a, hipStream_t st) {
         return fail(SAGMS_EUNSUPPORTED, "decode layout mismatch (internal)");
     if ((size_t)a.L.words * sizeof(float) > 65536) return fail(SAGMS_EUNSUPPORTED, "graph too large for one wave's LDS");
     const int wpb = waves_per_block(a.L);
-    int64_t waves = (a.nframes + a.frames_per_wave - 1) / a.frames_per_wave;
-    int64_t blocks = (waves + wpb - 1) / wpb;
-    if (blocks > 0x7fffffff) return fail(SAGMS_EINVAL, "too many frames for one launch");
-    size_t lds = (size_t)wpb * a.L.words * sizeof(float);
-    const dim3 grid((unsigned)blocks), block(64 * wpb);
+    const size_t lds = (size_t)wpb * a.L.words * sizeof(float);
+    int rc;
     if (bp)
-        launch_one<DC, DV, CPL, VPL, true, SAGMS_MSG_FP32>(grid, block, lds, st, a);
+        rc = launch_kernel<DC, DV, CPL, VPL, true, SAGMS_MSG_FP32>(a, wpb, lds, st);
     else if (mt == SAGMS_MSG_FP16)
-        launch_one<DC, DV, CPL, VPL, false, SAGMS_MSG_FP16>(grid, block, lds, st, a);
+        rc = launch_kernel<DC, DV, CPL, VPL, false, SAGMS_MSG_FP16>(a, wpb, lds, st);
     else if (mt == SAGMS_MSG_INT6)
-        launch_one<DC, DV, CPL, VPL, false, SAGMS_MSG_INT6>(grid, block, lds, st, a);
+        rc = launch_kernel<DC, DV, CPL, VPL, false, SAGMS_MSG_INT6>(a, wpb, lds, st);
     else
-        launch_one<DC, DV, CPL, VPL, false, SAGMS_MSG_FP32>(grid, block, lds, st, a);
+        rc = launch_kernel<DC, DV, CPL, VPL, false, SAGMS_MSG_FP32>(a, wpb, lds, st);
+    if (rc) return rc;
     SAGMS_HIP(hipGetLastError());
     return SAGMS_OK;
 }

@@ -136,7 +136,8 @@ struct DecodeArgs {
 };
 int launch_decode(const DecodeShape& s, bool bp, int msg_precision, const DecodeArgs& a, hipStream_t st);
 
-constexpr int kDecodeFramesPerWave = 8;
+constexpr int kDecodeFramesPerWave = 16;  // frames per wave before the taper
+constexpr int kMixedTileFrames = 8;       // default tile of a mixed-code batch
 // Decoder configuration checks (api.cpp); SAGMS_OK or a status.
 int check_cfg(const sagms_decoder_cfg* c);
 // Device gain table of a configuration on the current device.

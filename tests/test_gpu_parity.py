@@ -476,6 +476,32 @@ def test_decode_launch_shape_does_not_change_results(dev, fpw):
         assert (x.view(np.uint8) == y.view(np.uint8)).all()
 
 
+@pytest.mark.parametrize("name,nf", [("G63", 300_001), ("G63", 16_385), ("G127", 140_000), ("G511w5", 40_000)])
+def test_tapered_launch_covers_every_frame(dev, name, nf):
+    """The default launch's tapered frame assignment (runs of 16 frames, then
+    8, 4, 2 and 1 at the end of the grid) decodes every frame exactly as a
+    launch with one frame per wave does, on batches that span every level
+    of the taper; outputs start as a sentinel, so a frame left out shows."""
+    l, a, b = workloads.code(name)
+    g = sagms.Graph.gb(l, a, b)
+    p = 0.06
+    buf = sagms.frame_buffers(g, nf, device=dev)
+    sagms.gen_errors(g, 3, 7, 0, nf, p, buf["ex"], buf["ez"], buf["synd"])
+    llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
+    outs = []
+    for fpw in (0, 1):
+        e = torch.full((nf, g.words_n), -1, dtype=torch.int64, device=dev)
+        it = torch.full((nf,), -7, dtype=torch.int32, device=dev)
+        cv = torch.full((nf,), 9, dtype=torch.uint8, device=dev)
+        say("taper", name, nf, fpw)
+        sagms.decode(g, buf["synd"], llr, sagms.decoder_config("sagms", frames_per_wave=fpw), e, it, cv)
+        torch.cuda.synchronize()
+        outs.append((e.cpu().numpy(), it.cpu().numpy(), cv.cpu().numpy()))
+    (e0, i0, c0), (e1, i1, c1) = outs
+    assert (i1 >= 0).all() and (c1 <= 1).all()
+    assert (e0 == e1).all() and (i0 == i1).all() and (c0 == c1).all()
+
+
 C1 = None
 
 
