@@ -1,18 +1,20 @@
 // Logical-failure judge: frame f fails iff it did not converge or the
 // residual r = e_x xor e_hat has odd overlap with a row of the logical basis
 // (a basis of ker(H_other) modulo rowspace(H)), i.e. r is not a stabilizer.
-// A bounded grid of blocks strides over the frames, one frame per thread at
-// a time: the residual words stay in registers, the basis is staged in LDS
-// (read at wave-uniform addresses) and every row's parity is evaluated
-// without an early exit.  Failure and round counts are reduced per thread,
-// then per block, and added with one atomic per block and counter (atomics
-// on one address serialise, so their number is kept to the grid size).
+// A bounded grid of blocks strides over the frames, kJudgeUnroll frames per
+// thread at a time with all their loads issued before any is used: the
+// residual words stay in registers, the basis is staged in LDS (read at
+// wave-uniform addresses) and every row's parity is evaluated without an
+// early exit.  Failure and round counts are reduced per thread, then per
+// block, and added with one atomic per block and counter.  Atomics on one
+// address serialise (about 10 ns each on this GPU: 2048 of them took half of
+// a 2^20-frame judge), so the grid is at most 256 blocks of 1024 threads.
 #include "internal.h"
 
 namespace sagms {
 
-constexpr int kJudgeBlock = 256;
-constexpr int kJudgeMaxBlocks = 1024;
+constexpr int kJudgeBlock = 1024;
+constexpr int kJudgeMaxBlocks = 256;
 constexpr size_t kJudgeLdsMax = 32768;
 
 __device__ __forceinline__ bool judge_frame_any(const JudgeArgs& a, int64_t f) {
@@ -27,11 +29,12 @@ __device__ __forceinline__ bool judge_frame_any(const JudgeArgs& a, int64_t f) {
     return a.conv[f] == 0 || (odd & 1u);
 }
 
+constexpr int kJudgeUnroll = 4;
+
+// Parity of the residual r against every basis row: 1 iff some row has odd
+// overlap.
 template <int WN>
-__device__ __forceinline__ bool judge_frame(const JudgeArgs& a, const uint64_t* lg, int64_t f) {
-    uint64_t r[WN];
-#pragma unroll
-    for (int w = 0; w < WN; ++w) r[w] = w < a.wn ? a.ex[f * a.wn + w] ^ a.ehat[f * a.wn + w] : 0ull;
+__device__ __forceinline__ uint32_t judge_odd(const JudgeArgs& a, const uint64_t* lg, const uint64_t (&r)[WN]) {
     uint32_t odd = 0;
     for (int t = 0; t < a.k; ++t) {
         uint32_t cnt = 0;
@@ -40,7 +43,7 @@ __device__ __forceinline__ bool judge_frame(const JudgeArgs& a, const uint64_t* 
             if (w < a.wn) cnt += __builtin_popcountll(r[w] & lg[t * a.wn + w]);
         odd |= cnt;
     }
-    return a.conv[f] == 0 || (odd & 1u);
+    return odd & 1u;
 }
 
 // WN = 0: basis and residual read from global memory (any size).
@@ -54,15 +57,39 @@ __global__ void __launch_bounds__(kJudgeBlock) judge_kernel(JudgeArgs a) {
     }
     const int64_t stride = (int64_t)gridDim.x * kJudgeBlock;
     uint64_t nfail = 0, isum = 0;
-    for (int64_t f = (int64_t)blockIdx.x * kJudgeBlock + threadIdx.x; f < a.nframes; f += stride) {
-        bool failed;
-        if constexpr (WN > 0)
-            failed = judge_frame<WN>(a, lg, f);
-        else
-            failed = judge_frame_any(a, f);
-        if (a.fail) a.fail[f] = failed ? 1 : 0;
-        nfail += failed ? 1 : 0;
-        isum += (uint64_t)a.iters[f];
+    if constexpr (WN > 0) {
+        for (int64_t f0 = (int64_t)blockIdx.x * kJudgeBlock + threadIdx.x; f0 < a.nframes;
+             f0 += kJudgeUnroll * stride) {
+            uint64_t r[kJudgeUnroll][WN];
+            uint8_t conv[kJudgeUnroll];
+            int32_t it[kJudgeUnroll];
+#pragma unroll
+            for (int u = 0; u < kJudgeUnroll; ++u) {
+                const int64_t f = f0 + u * stride;
+                const bool in = f < a.nframes;
+#pragma unroll
+                for (int w = 0; w < WN; ++w)
+                    r[u][w] = in && w < a.wn ? a.ex[f * a.wn + w] ^ a.ehat[f * a.wn + w] : 0ull;
+                conv[u] = in ? a.conv[f] : 1;
+                it[u] = in ? a.iters[f] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kJudgeUnroll; ++u) {
+                const int64_t f = f0 + u * stride;
+                if (f >= a.nframes) break;
+                const bool failed = conv[u] == 0 || judge_odd<WN>(a, lg, r[u]);
+                if (a.fail) a.fail[f] = failed ? 1 : 0;
+                nfail += failed ? 1 : 0;
+                isum += (uint64_t)it[u];
+            }
+        }
+    } else {
+        for (int64_t f = (int64_t)blockIdx.x * kJudgeBlock + threadIdx.x; f < a.nframes; f += stride) {
+            const bool failed = judge_frame_any(a, f);
+            if (a.fail) a.fail[f] = failed ? 1 : 0;
+            nfail += failed ? 1 : 0;
+            isum += (uint64_t)a.iters[f];
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         nfail += __shfl_xor(nfail, off, 64);
