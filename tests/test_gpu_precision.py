@@ -7,7 +7,8 @@ the fraction of frames whose hard decision differs from FP64.  Asserted:
 FP32 and FP16 agree with FP64 on nearly every frame; INT6's FER lies within
 the Wilson interval of the FP64 FER on the same frames, widened by the
 coarse grid's own effect (checked only where FP64 converges on most frames).
-The records go to gpurun_out/precision_mix.json when that folder exists.
+With SAGMS_RECORD_DIR set, the records are written to precision_mix.json
+in that folder.
 """
 import json
 import os
@@ -31,8 +32,8 @@ def dev():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     yield torch.device("cuda:0")
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if RECORDS and os.path.isdir(out):
+    out = os.environ.get("SAGMS_RECORD_DIR")
+    if RECORDS and out and os.path.isdir(out):
         with open(os.path.join(out, "precision_mix.json"), "w") as fh:
             json.dump(RECORDS, fh, indent=1)
 
