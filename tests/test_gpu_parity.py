@@ -502,6 +502,28 @@ def test_tapered_launch_covers_every_frame(dev, name, nf):
     assert (e0 == e1).all() and (i0 == i1).all() and (c0 == c1).all()
 
 
+def test_batches_beyond_one_launch_are_refused(dev):
+    """A batch whose grid would exceed 2^31 - 1 blocks (2^50 frames) is
+    refused with SAGMS_EINVAL before any kernel runs, by the sampler and by
+    the decoder (default and uniform launches); the buffers passed are small
+    and valid, and are never touched."""
+    import ctypes
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    small = torch.zeros(64, dtype=torch.int64, device=dev)
+    llr = torch.full((g.n,), 3.0, dtype=torch.float32, device=dev)
+    ptr = ctypes.c_void_p(small.data_ptr())
+    huge = 1 << 50
+    L = sagms.lib()
+    rc = L.sagms_gen_errors(g._h, 1, 0, 0, huge, 0.05, ptr, ptr, ptr, None)
+    assert rc == -1 and "too many frames" in L.sagms_last_error().decode()
+    for fpw in (0, 1, 1024):
+        cfg = sagms.decoder_config("sagms", frames_per_wave=fpw)
+        rc = L.sagms_decode(g._h, ptr, ctypes.c_void_p(llr.data_ptr()), ctypes.byref(cfg), huge, ptr, ptr, ptr, None)
+        assert rc == -1 and "too many frames" in L.sagms_last_error().decode()
+    torch.cuda.synchronize()
+    assert (small == 0).all()
+
+
 C1 = None
 
 
