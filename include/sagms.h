@@ -129,7 +129,10 @@ int sagms_build_graph(int32_t m, int32_t n, const int32_t* row_ptr_host, const i
  * bicycle family).  Circulant convention A[i][j] = 1 iff (j - i) mod l is an
  * exponent of a.  Builds the decoding matrix H = H_Z = [B^T | A^T] and the
  * other matrix H_X = [A | B], so that X errors are decoded from their H_Z
- * syndrome.  n = 2l, m = l. */
+ * syndrome.  n = 2l, m = l.  The decoder's FP32 posterior of a variable sums
+ * its checks in the order of the polynomial terms as given: variable i < l
+ * meets checks (i + b_t) mod l for t = 0, 1, ..., variable l + i meets
+ * (i + a_t) mod l (sagms_build_graph: ascending check index). */
 int sagms_build_gb(int32_t l, const int32_t* a_host, int32_t wa, const int32_t* b_host, int32_t wb,
                    sagms_graph* out);
 
@@ -190,8 +193,9 @@ int sagms_gen_errors(sagms_graph g, uint64_t seed, uint32_t stream_id, uint64_t 
  * Each round: gains from the residual syndrome, CN update (eq. (ms_cn),
  * scaled per eq. (alphaeff)/(sagms_cn), or eq. (bp4_cn) for BP), VN update
  * (eq. (bp4_vn)), hard decision e_j = [posterior_j < 0], residual syndrome,
- * exit when it is zero.  Messages are FP32; posteriors are summed in
- * ascending check order and v2c = posterior - c2v; the BP CN runs in FP64.
+ * exit when it is zero.  Messages are FP32; each posterior is summed in
+ * its graph's check order (see the two graph builders) and v2c =
+ * posterior - c2v; the BP CN runs in FP64.
  * Per-frame results do not depend on nframes, the batch split or the
  * stream.  nframes >= 0. */
 int sagms_decode(sagms_graph g, const uint64_t* synd, const float* llr0, const sagms_decoder_cfg* cfg,
