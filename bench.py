@@ -488,6 +488,8 @@ def main():
                     help="build the code from its polynomials (posteriors summed in polynomial-term order) or "
                          "from the rows of H_Z (ascending check order)")
     ap.add_argument("--frames-per-wave", type=int, default=0, help="decode launch shape (0 = library default)")
+    ap.add_argument("--schedule", default="flooding", choices=["flooding", "layered"],
+                    help="message-passing schedule of the single-code workload (Algorithm 1 floods)")
     ap.add_argument("--pipeline", dest="pipeline", action="store_true", default=None,
                     help="run the sampler of step s + 1 on a second stream while step s decodes, on two sets of "
                          "frame buffers (default for the single-code workload)")
@@ -536,16 +538,17 @@ def main():
     l, a, b = workloads.code("G63")
     if args.graph == "gb":
         g = sagms.Graph.gb(l, a, b)
-        kernel = "decode_kernel<10,5,1,2,%s>" % ("true" if args.decoder == "bp" else "false")
     else:
         g = sagms.Graph.from_dense(*gb_dense(l, a, b))
-        kernel = "decode_kernel<10,5,1,2,%s>" % ("true" if args.decoder == "bp" else "false")
+    kernel = "decode_kernel<10,5,1,2,%s>" % ("true" if args.decoder == "bp" else "false")
+    if args.schedule == "layered":
+        kernel = "layered_kernel<10,8>"
     nf, p = args.frames, args.p
     stream_id = workloads.stream_of(p) if p in workloads.P_GRID else 0
     bufs = [sagms.frame_buffers(g, nf, device=dev) for _ in range(2 if args.pipeline else 1)]
     llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
     cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, frames_per_wave=args.frames_per_wave,
-                               **workloads.SAGMS_PARAMS)
+                               schedule=args.schedule, **workloads.SAGMS_PARAMS)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
     # --pipeline: the sampler of step s + 1 runs on a second stream while step
@@ -642,10 +645,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "GB l=63 [[126,28]] (H_Z: m=63, d_c=10, d_v=5, E=630), code-capacity depolarizing "
-                               "p=%g, %d Philox frames/step, %s l_max=%d early exit, flooding, FP32 messages"
-                               % (p, nf, args.decoder.upper(), args.lmax),
+                               "p=%g, %d Philox frames/step, %s l_max=%d early exit, %s, FP32 messages"
+                               % (p, nf, args.decoder.upper(), args.lmax, args.schedule),
                    "code": "G63", "graph": args.graph, "frames_per_wave": args.frames_per_wave, "p": p, "frames_per_step": nf, "decoder": args.decoder, "lmax": args.lmax,
-                   "pipeline": bool(args.pipeline)},
+                   "schedule": args.schedule, "pipeline": bool(args.pipeline)},
         "edge_updates_per_s": edge_updates / (total_ms * 1e-3),
         "decode_ms_per_step": mean_dec_ms,
         "decode_frames_per_s": nf / (mean_dec_ms * 1e-3),
@@ -656,7 +659,8 @@ def main():
         "wall_s": wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": measured_traffic(nf, p) if args.graph == "gb" and args.decoder == "sagms" else None,
+                     "traffic": measured_traffic(nf, p) if (args.graph == "gb" and args.decoder == "sagms"
+                                                            and args.schedule == "flooding") else None,
                      "kernel": kernel,
                      "ops_per_edge_update": OPS_PER_EDGE_UPDATE,
                      "note": "decode launch time inside the pipelined steps (the next step's sampler shares the GPU)"

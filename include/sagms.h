@@ -50,7 +50,26 @@ typedef enum {
     SAGMS_BP = 3     /* belief propagation, eq. (bp4_cn) (comparison)       */
 } sagms_kind;
 
-typedef enum { SAGMS_FLOODING = 0 } sagms_schedule;
+/* Message-passing schedule.
+ *   FLOODING  Algorithm 1: every check updates from the previous round's
+ *             variable messages, then every variable.
+ *   LAYERED   (not in the paper; this library's reading) the checks are
+ *             split into layers of checks with pairwise disjoint supports,
+ *             by first fit in ascending check index, and a round visits the
+ *             layers in order: each check of a layer takes v2c = posterior
+ *             - its own previous output (FP32), computes its output by the
+ *             same check rule and gains as FLOODING, and sets posterior =
+ *             v2c + new output, so later layers see earlier layers' updates
+ *             within the round.  Gains, hard decisions, the residual test
+ *             and the round count are as in FLOODING (gains from the
+ *             residual syndrome at the start of the round).  MS, SMS and
+ *             SAGMS with FP32 messages, sagms_decode / sagms_decode_soft
+ *             only, on graphs the flooding decoder supports whose checks
+ *             all have degree 6, 8 or 10 (SAGMS_EUNSUPPORTED otherwise).
+ *             Unscaled MS can overflow FP32 on frames that never converge;
+ *             IEEE infinities and NaNs then follow (a NaN posterior
+ *             decides 0).  frames_per_wave is ignored. */
+typedef enum { SAGMS_FLOODING = 0, SAGMS_LAYERED = 1 } sagms_schedule;
 
 /* Message formats (posteriors are always FP32 sums of the messages):
  *   FP32  FP32 messages; BP evaluates its CN in FP64

@@ -27,6 +27,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sagms.h")
 OK, EINVAL, ENOMEM, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
 KINDS = {"ms": 0, "sms": 1, "sagms": 2, "bp": 3}
 PRECISIONS = {"fp32": 0, "fp16": 1, "int6": 2}
+SCHEDULES = {"flooding": 0, "layered": 1}
 
 _lib = None
 
@@ -155,13 +156,15 @@ def derived_config(l0, dc, ratio=0.6, eta=0.0, lmax=100, frames_per_wave=0, prec
 
 
 def decoder_config(kind="sagms", lmax=100, alpha=0.75, alpha_min=0.30, alpha_max=0.50, eta=1.10,
-                   frames_per_wave=0, precision="fp32") -> DecoderConfig:
+                   frames_per_wave=0, precision="fp32", schedule="flooding") -> DecoderConfig:
     if kind not in KINDS:
         raise ValueError("unknown decoder kind %r" % kind)
     if precision not in PRECISIONS:
         raise ValueError("unknown message precision %r" % precision)
-    return DecoderConfig(KINDS[kind], 0, int(lmax), PRECISIONS[precision], float(alpha), float(alpha_min),
-                         float(alpha_max), float(eta), int(frames_per_wave), 0)
+    if schedule not in SCHEDULES:
+        raise ValueError("unknown schedule %r" % schedule)
+    return DecoderConfig(KINDS[kind], SCHEDULES[schedule], int(lmax), PRECISIONS[precision], float(alpha),
+                         float(alpha_min), float(alpha_max), float(eta), int(frames_per_wave), 0)
 
 
 class Graph:

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsagms.so")
-SOURCES = ["graph.cpp", "api.cpp", "batch.cpp", "serve.cpp", "decode.hip", "mixed.hip", "sample.hip", "judge.hip"]
+SOURCES = ["graph.cpp", "api.cpp", "batch.cpp", "serve.cpp", "layers.cpp", "decode.hip", "mixed.hip", "sample.hip",
+           "judge.hip", "layered.hip"]
 ARCH = "gfx950"
 
 

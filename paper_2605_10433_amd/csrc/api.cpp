@@ -16,7 +16,10 @@ namespace sagms {
 int check_cfg(const sagms_decoder_cfg* c) {
     if (!c) return fail(SAGMS_EINVAL, "cfg is null");
     if (c->kind < SAGMS_MS || c->kind > SAGMS_BP) return fail(SAGMS_EINVAL, "unknown decoder kind %d", c->kind);
-    if (c->schedule != SAGMS_FLOODING) return fail(SAGMS_EUNSUPPORTED, "only the flooding schedule is implemented");
+    if (c->schedule != SAGMS_FLOODING && c->schedule != SAGMS_LAYERED)
+        return fail(SAGMS_EINVAL, "unknown schedule %d", c->schedule);
+    if (c->schedule == SAGMS_LAYERED && (c->kind == SAGMS_BP || c->msg_precision != SAGMS_MSG_FP32))
+        return fail(SAGMS_EUNSUPPORTED, "the layered schedule runs MS, SMS and SAGMS with FP32 messages");
     if (c->msg_precision < SAGMS_MSG_FP32 || c->msg_precision > SAGMS_MSG_INT6)
         return fail(SAGMS_EUNSUPPORTED, "message precision %d not available", c->msg_precision);
     if (c->kind == SAGMS_BP && c->msg_precision != SAGMS_MSG_FP32)
@@ -138,6 +141,12 @@ int sagms_decode_soft(sagms_graph gh, const uint64_t* synd, const float* llr0, c
     if (rc) return rc;
     const DecodeArgs a = decode_args(g, t, gains, synd, llr0, nframes, ehat, iters, converged, posterior, cfg->lmax,
                                      cfg->frames_per_wave);
+    if (cfg->schedule == SAGMS_LAYERED) {
+        const LayeredPlan* plan = nullptr;
+        rc = layered_plan(g, t, &plan, st);
+        if (rc) return rc;
+        return launch_layered(*plan, a, st);
+    }
     return launch_decode(g->shape, cfg->kind == SAGMS_BP, cfg->msg_precision, a, st);
 }
 

@@ -173,6 +173,7 @@ int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_deco
     int rc = check_cfg(cfg);
     if (rc) return rc;
     if (cfg->kind == SAGMS_BP) return fail(SAGMS_EUNSUPPORTED, "batches run MS, SMS and SAGMS only");
+    if (cfg->schedule != SAGMS_FLOODING) return fail(SAGMS_EUNSUPPORTED, "batches run the flooding schedule only");
     for (int s = 0; s < nseg; ++s) {
         const sagms_segment& x = segs[s];
         Graph* g = reinterpret_cast<Graph*>(x.graph);

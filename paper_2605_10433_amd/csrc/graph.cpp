@@ -439,6 +439,11 @@ int sagms_destroy_graph(sagms_graph gh) {
         (void)hipFree(t.vn_addr);
         (void)hipFree(t.logicals);
         for (auto& kv : t.gains) (void)hipFree(kv.second);
+        if (t.layered) {
+            (void)hipFree(t.layered->pass_check);
+            (void)hipFree(t.layered->check_vars);
+            delete t.layered;
+        }
     }
     if (have_dev) (void)hipSetDevice(cur);
     delete g;

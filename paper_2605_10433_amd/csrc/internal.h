@@ -74,8 +74,22 @@ struct GainKey {
     }
 };
 
+// Layered schedule (layered.hip, layers.cpp): the checks in layers of checks
+// with disjoint supports (first fit in ascending check index), every layer
+// cut into passes of at most `group` checks; a wavefront decodes 64 / group
+// frames, one per group of `group` lanes.  LDS words per wavefront: the
+// shared tables (pass table, variable pairs, gains, prior), then per frame
+// the posteriors (npad words), the c2v messages (m * dc) and the syndrome
+// and residual bits (2 * wm words each).
+struct LayeredPlan {
+    int dc = 0, group = 0, passes = 0, npad = 0, group_words = 0, table_words = 0;
+    int32_t* pass_check = nullptr;   // device [passes][group], -1 = idle lane
+    uint32_t* check_vars = nullptr;  // device [m][dc / 2] variable pairs
+};
+
 struct DeviceTables {
     bool ready = false;
+    LayeredPlan* layered = nullptr;  // created on the first layered decode
     uint32_t* cn_addr = nullptr;   // [cpl * dc][64] LDS word index of the posterior read at (check, pos)
     uint32_t* vn_addr = nullptr;   // [vpl * dv][64] LDS word index of the c2v slot read at (var, rank)
     int32_t* cols = nullptr;       // [m][dc_max] column of (check, pos), -1 padded (sampler)
@@ -135,6 +149,9 @@ struct DecodeArgs {
     DecodeLayout L;
 };
 int launch_decode(const DecodeShape& s, bool bp, int msg_precision, const DecodeArgs& a, hipStream_t st);
+// The layered plan of g on the current device (created once; layers.cpp).
+int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t st);
+int launch_layered(const LayeredPlan& plan, const DecodeArgs& a, hipStream_t st);
 
 constexpr int kDecodeFramesPerWave = 16;  // frames per wave before the taper
 constexpr int kMixedTileFrames = 8;       // default tile of a mixed-code batch

@@ -1,0 +1,262 @@
+// Layered-schedule decoder: the check-serial alternative to the flooding
+// schedule of Algorithm 1 (the paper defines only flooding; the reading
+// implemented here is stated with SAGMS_LAYERED in sagms.h).
+//
+// The host splits the checks into layers of checks with pairwise disjoint
+// supports (first fit in ascending check index) and every layer into passes
+// of at most G checks.  A wavefront decodes F = 64 / G frames at once, one
+// per group of G lanes.  In pass p, lane q of a group updates check
+// pass_check[p][q] of its frame: it reads its variables' posteriors and its
+// own previous outputs from LDS, forms v2c = posterior - c2v_old, computes
+// the check output exactly as the flooding decoder does (cn_update), and
+// writes c2v_new and posterior = v2c + c2v_new back.  The checks of one pass
+// touch disjoint variables, and one wavefront's LDS operations complete in
+// order, so the passes need no barrier.  After the last pass every lane
+// recomputes the residual-syndrome bits of the checks q, q + G, ... from the
+// hard decisions; the weight gives the next round's gains and the exit test.
+//
+// A wavefront owns a contiguous run of frames.  Each group holds one frame
+// in decoding and one reserved next frame whose syndrome words are already
+// in flight; a group that finishes starts its reserved frame and reserves
+// the next unclaimed frame of the run, so groups stay busy until the run is
+// used up whatever their frames' round counts.
+#include "decode_core.h"
+
+namespace sagms {
+
+struct LayeredArgs {
+    DecodeArgs a;
+    const int32_t* pass_check;   // [P][G] check of (pass, lane), -1 = idle
+    const uint32_t* check_vars;  // [m][DC / 2] variable pairs (low, high 16 bits)
+    int64_t frames_per_wave;
+    int P, npad, gwords, tables;  // tables: LDS words in front of the group slices
+};
+
+template <int G>
+__device__ __forceinline__ uint64_t group_segment(uint64_t ballot, int grp) {
+    if constexpr (G == 64) {
+        return ballot;
+    } else {
+        return (ballot >> (grp * G)) & ((1ull << G) - 1);
+    }
+}
+
+template <int DC, int G>
+__global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
+    constexpr int F = 64 / G;
+    static_assert(F * G == 64, "G must divide 64");
+    extern __shared__ uint32_t lds_u[];
+    const DecodeArgs& a = la.a;
+    const int lane = threadIdx.x;
+    const int grp = lane / G, q = lane % G;
+    const int m = a.m, n = a.n, wm = a.wm, wn = a.wn;
+
+    uint32_t* t_pass = lds_u;
+    uint32_t* t_vars = t_pass + la.P * G;
+    float* t_gain = reinterpret_cast<float*>(t_vars + m * (DC / 2));
+    float* t_l0 = t_gain + 2 * (m + 1);
+    float* post = reinterpret_cast<float*>(lds_u + la.tables + grp * la.gwords);
+    float* c2v = post + la.npad;
+    uint32_t* sbits = reinterpret_cast<uint32_t*>(c2v + m * DC);
+    uint32_t* rbits = sbits + 2 * wm;
+
+    for (int t = lane; t < la.P * G; t += 64) t_pass[t] = (uint32_t)la.pass_check[t];
+    for (int t = lane; t < m * (DC / 2); t += 64) t_vars[t] = la.check_vars[t];
+    for (int t = lane; t < 2 * (m + 1); t += 64) t_gain[t] = a.gains[t];
+    for (int t = lane; t < n; t += 64) t_l0[t] = a.llr0[t] + 0.0f;  // -0 reads as +0
+    __syncthreads();
+
+    const int64_t f_begin = (int64_t)blockIdx.x * la.frames_per_wave;
+    const int64_t f_end = min(f_begin + la.frames_per_wave, a.nframes);
+    if (f_begin >= f_end) return;
+
+    // group state (equal in the G lanes of a group)
+    int64_t f = -1;                              // frame being decoded
+    int64_t res = f_begin + grp < f_end ? f_begin + grp : -1;  // reserved next frame
+    int64_t next = f_begin + F;                  // wave-uniform: next unclaimed frame
+    uint64_t res_word = 0;                       // lanes q < wm: word q of res's syndrome
+    if (res >= 0 && q < wm) res_word = a.synd[res * wm + q];
+    int it = 0, w = 0;
+    bool active = false;
+
+    // Residual bits of the group's frame from its posteriors; returns the
+    // weight.  Executed by the lanes of the groups in `on`.
+    auto residual = [&](bool on) -> int {
+        int weight = 0;
+        for (int r = 0; r * G < m; ++r) {
+            const int c = r * G + q;
+            bool bit = false;
+            if (on && c < m) {
+                uint32_t par = (sbits[c >> 5] >> (c & 31)) & 1u;
+#pragma unroll
+                for (int k = 0; k < DC / 2; ++k) {
+                    const uint32_t pv = t_vars[c * (DC / 2) + k];
+                    par ^= __float_as_uint(post[pv & 0xFFFFu]) >> 31;
+                    par ^= __float_as_uint(post[pv >> 16]) >> 31;
+                }
+                bit = par != 0;
+            }
+            const uint64_t seg = group_segment<G>(__ballot(bit), grp);
+            weight += __popcll(seg);
+            if (on && q == 0) {
+                if constexpr (G == 64) {
+                    rbits[2 * r] = (uint32_t)seg;
+                    rbits[2 * r + 1] = (uint32_t)(seg >> 32);
+                } else if constexpr (G == 32) {
+                    rbits[r] = (uint32_t)seg;
+                } else if constexpr (G == 16) {
+                    reinterpret_cast<uint16_t*>(rbits)[r] = (uint16_t)seg;
+                } else {
+                    reinterpret_cast<uint8_t*>(rbits)[r] = (uint8_t)seg;
+                }
+            }
+        }
+        return weight;
+    };
+
+    // Outputs of the group's frame (groups in `on`): hard decisions, rounds,
+    // flag and, when asked for, the posteriors.
+    auto finish = [&](bool on, int rounds, bool conv) {
+        uint64_t word = 0;
+        for (int r = 0; r * G < n; ++r) {
+            const int j = r * G + q;
+            const bool neg = on && j < n && post[j] < 0.0f;
+            const uint64_t seg = group_segment<G>(__ballot(neg), grp);
+            const int bit0 = r * G;
+            if (q == (bit0 >> 6)) word |= seg << (bit0 & 63);
+        }
+        if (on) {
+            if (q < wn) a.ehat[f * wn + q] = word;
+            if (q == 0) {
+                a.iters[f] = rounds;
+                a.conv[f] = conv ? 1 : 0;
+            }
+            if (a.post)
+                for (int j = q; j < n; j += G) a.post[f * n + j] = post[j];
+        }
+    };
+
+    while (true) {
+        // start reserved frames in idle groups, reserve the next ones, and
+        // finish frames that need no round, until no idle group holds one
+        while (true) {
+            const bool start = !active && res >= 0;
+            const uint64_t leaders = __ballot(start && q == 0);
+            if (leaders == 0) break;
+            if (start) {
+                f = res;
+                for (int j = q; j < n; j += G) post[j] = t_l0[j];
+                for (int t = q; t < m * DC; t += G) c2v[t] = 0.0f;
+                if (q < wm) {
+                    sbits[2 * q] = (uint32_t)res_word;
+                    sbits[2 * q + 1] = (uint32_t)(res_word >> 32);
+                }
+                const int rank = __popcll(leaders & ((1ull << (grp * G)) - 1));
+                const int64_t claim = next + rank;
+                res = claim < f_end ? claim : -1;
+                if (res >= 0 && q < wm) res_word = a.synd[res * wm + q];
+            }
+            next += __popcll(leaders);
+            const int w0 = residual(start);
+            if (start) {
+                w = w0;
+                it = 0;
+                active = w0 != 0;
+            }
+            finish(start && w0 == 0, 0, true);
+        }
+        if (__ballot(active) == 0) break;
+
+        // one round: every layer of checks, pass by pass
+        const float gs = t_gain[2 * w], gu = t_gain[2 * w + 1];
+        for (int p = 0; p < la.P; ++p) {
+            const int c = (int)t_pass[p * G + q];
+            if (active && c >= 0) {
+                uint32_t var[DC];
+#pragma unroll
+                for (int k = 0; k < DC / 2; ++k) {
+                    const uint32_t pv = t_vars[c * (DC / 2) + k];
+                    var[2 * k] = pv & 0xFFFFu;
+                    var[2 * k + 1] = pv >> 16;
+                }
+                float v[DC], out[DC];
+#pragma unroll
+                for (int k = 0; k < DC; ++k) v[k] = post[var[k]] - c2v[c * DC + k];
+                const uint32_t sb = ((sbits[c >> 5] >> (c & 31)) & 1u) << 31;
+                const bool unsat = (rbits[c >> 5] >> (c & 31)) & 1u;
+                cn_update<DC, false, SAGMS_MSG_FP32>(v, sb, unsat, gs, gu, out);
+#pragma unroll
+                for (int k = 0; k < DC; ++k) {
+                    c2v[c * DC + k] = out[k];
+                    post[var[k]] = v[k] + out[k];
+                }
+            }
+        }
+        const int w1 = residual(active);
+        bool done = false;
+        if (active) {
+            ++it;
+            w = w1;
+            done = w1 == 0 || it >= a.lmax;
+        }
+        finish(done, it, w1 == 0);
+        if (done) active = false;
+    }
+}
+
+namespace {
+
+template <int DC, int G>
+int launch_dg(const LayeredArgs& la, size_t lds, int num_cu, hipStream_t st) {
+    const void* fn = reinterpret_cast<const void*>(&layered_kernel<DC, G>);
+    int per_cu = 0;
+    SAGMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds));
+    if (per_cu < 1) return fail(SAGMS_EUNSUPPORTED, "layered kernel does not fit a compute unit");
+    constexpr int F = 64 / G;
+    const int64_t groups_needed = (la.a.nframes + F - 1) / F;
+    int64_t waves = std::min<int64_t>((int64_t)per_cu * num_cu, groups_needed);
+    LayeredArgs x = la;
+    x.frames_per_wave = (la.a.nframes + waves - 1) / waves;
+    waves = (la.a.nframes + x.frames_per_wave - 1) / x.frames_per_wave;
+    hipLaunchKernelGGL((layered_kernel<DC, G>), dim3((unsigned)waves), dim3(64), lds, st, x);
+    SAGMS_HIP(hipGetLastError());
+    return SAGMS_OK;
+}
+
+template <int DC>
+int launch_d(int G, const LayeredArgs& la, size_t lds, int num_cu, hipStream_t st) {
+    switch (G) {
+        case 8: return launch_dg<DC, 8>(la, lds, num_cu, st);
+        case 16: return launch_dg<DC, 16>(la, lds, num_cu, st);
+        case 32: return launch_dg<DC, 32>(la, lds, num_cu, st);
+        case 64: return launch_dg<DC, 64>(la, lds, num_cu, st);
+        default: return fail(SAGMS_EUNSUPPORTED, "layered group size %d (internal)", G);
+    }
+}
+
+}  // namespace
+
+int launch_layered(const LayeredPlan& plan, const DecodeArgs& a, hipStream_t st) {
+    if (a.nframes <= 0) return SAGMS_OK;
+    LayeredArgs la{};
+    la.a = a;
+    la.pass_check = plan.pass_check;
+    la.check_vars = plan.check_vars;
+    la.P = plan.passes;
+    la.npad = plan.npad;
+    la.gwords = plan.group_words;
+    la.tables = plan.table_words;
+    const int F = 64 / plan.group;
+    const size_t lds = (size_t)(plan.table_words + F * plan.group_words) * sizeof(uint32_t);
+    int dev = 0, num_cu = 0;
+    SAGMS_HIP(hipGetDevice(&dev));
+    SAGMS_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    switch (plan.dc) {
+        case 6: return launch_d<6>(plan.group, la, lds, num_cu, st);
+        case 8: return launch_d<8>(plan.group, la, lds, num_cu, st);
+        case 10: return launch_d<10>(plan.group, la, lds, num_cu, st);
+        default: return fail(SAGMS_EUNSUPPORTED, "layered schedule: check degree %d not compiled", plan.dc);
+    }
+}
+
+}  // namespace sagms

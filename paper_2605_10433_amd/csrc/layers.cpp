@@ -1,0 +1,105 @@
+// Host side of the layered schedule: the layers of a graph (first fit in
+// ascending check index: check i joins the first layer none of whose checks
+// shares a variable with it, else opens a new one), their passes of at most
+// `group` checks, and the device tables of layered.hip.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace sagms {
+
+namespace {
+
+constexpr int kLayeredMaxLds = 65536;
+
+int round4(int x) { return (x + 3) & ~3; }
+
+}  // namespace
+
+int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t st) {
+    std::lock_guard<std::mutex> lock(g->mu);
+    if (t->layered) {
+        *out = t->layered;
+        return SAGMS_OK;
+    }
+    const int m = g->m, n = g->n;
+    const int dc = g->row_ptr[1] - g->row_ptr[0];
+    for (int c = 0; c < m; ++c)
+        if (g->row_ptr[c + 1] - g->row_ptr[c] != dc)
+            return fail(SAGMS_EUNSUPPORTED, "layered schedule: needs every check of the same degree");
+    if (dc != 6 && dc != 8 && dc != 10)
+        return fail(SAGMS_EUNSUPPORTED, "layered schedule: check degree %d not compiled (6, 8 or 10)", dc);
+    if (n > 0xFFFF) return fail(SAGMS_EUNSUPPORTED, "layered schedule: n must be < 65536");
+
+    // first-fit layers
+    std::vector<std::vector<int>> layers;
+    std::vector<std::vector<char>> used;
+    for (int c = 0; c < m; ++c) {
+        size_t l = 0;
+        for (; l < layers.size(); ++l) {
+            bool clash = false;
+            for (int e = g->row_ptr[c]; e < g->row_ptr[c + 1] && !clash; ++e) clash = used[l][g->cols[e]] != 0;
+            if (!clash) break;
+        }
+        if (l == layers.size()) {
+            layers.emplace_back();
+            used.emplace_back(n, 0);
+        }
+        layers[l].push_back(c);
+        for (int e = g->row_ptr[c]; e < g->row_ptr[c + 1]; ++e) used[l][g->cols[e]] = 1;
+    }
+    size_t widest = 0;
+    for (const auto& l : layers) widest = std::max(widest, l.size());
+    // lanes per frame: the widest layer, the syndrome and estimate words
+    // (one lane each), a power of two up to a whole wavefront
+    const size_t need = std::max({widest, (size_t)g->wm, (size_t)g->wn});
+    int group = 8;
+    while (group < 64 && (size_t)group < need) group *= 2;
+    if ((size_t)g->wm > (size_t)group || (size_t)g->wn > (size_t)group)
+        return fail(SAGMS_EUNSUPPORTED, "layered schedule: code too long");
+
+    std::vector<int32_t> pass_check;
+    int passes = 0;
+    for (const auto& l : layers)
+        for (size_t b = 0; b < l.size(); b += group) {
+            for (int q = 0; q < group; ++q) pass_check.push_back(b + q < l.size() ? l[b + q] : -1);
+            ++passes;
+        }
+    std::vector<uint32_t> check_vars((size_t)m * (dc / 2));
+    for (int c = 0; c < m; ++c)
+        for (int k = 0; k < dc / 2; ++k)
+            check_vars[(size_t)c * (dc / 2) + k] =
+                (uint32_t)g->cols[g->row_ptr[c] + 2 * k] | ((uint32_t)g->cols[g->row_ptr[c] + 2 * k + 1] << 16);
+
+    auto* plan = new LayeredPlan();
+    plan->dc = dc;
+    plan->group = group;
+    plan->passes = passes;
+    plan->npad = round4(n);
+    plan->group_words = round4(plan->npad + m * dc + 4 * g->wm);
+    plan->table_words = round4(passes * group + m * (dc / 2) + 2 * (m + 1) + n);
+    const int frames = 64 / group;
+    if ((size_t)(plan->table_words + frames * plan->group_words) * 4 > (size_t)kLayeredMaxLds) {
+        delete plan;
+        return fail(SAGMS_EUNSUPPORTED, "layered schedule: code too large for one wavefront's LDS");
+    }
+    hipError_t e = hipMalloc(&plan->pass_check, pass_check.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&plan->check_vars, check_vars.size() * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(plan->pass_check, pass_check.data(), pass_check.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(plan->check_vars, check_vars.data(), check_vars.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (plan->pass_check) (void)hipFree(plan->pass_check);
+        if (plan->check_vars) (void)hipFree(plan->check_vars);
+        delete plan;
+        return hip_fail(e, "layered tables");
+    }
+    (void)st;
+    t->layered = plan;
+    *out = plan;
+    return SAGMS_OK;
+}
+
+}  // namespace sagms

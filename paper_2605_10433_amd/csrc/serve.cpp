@@ -270,6 +270,7 @@ int sagms_server_create(const sagms_graph* graphs, const float* const* llr0_host
     int rc = check_cfg(cfg);
     if (rc) return rc;
     if (cfg->kind == SAGMS_BP) return fail(SAGMS_EUNSUPPORTED, "the server runs MS, SMS and SAGMS only");
+    if (cfg->schedule != SAGMS_FLOODING) return fail(SAGMS_EUNSUPPORTED, "the server runs the flooding schedule only");
     if (!scfg) return fail(SAGMS_EINVAL, "server configuration is null");
     if (scfg->max_frames_per_launch < 1 || scfg->max_frames_per_launch > (1 << 24))
         return fail(SAGMS_EINVAL, "max_frames_per_launch must lie in [1, 2^24]");

@@ -108,8 +108,12 @@ def test_decoder_config_checks_before_device_work():
     bad.kind = 7
     assert _decode_rc(g, bad) == sagms.EINVAL
     sched = D("ms")
-    sched.schedule = 1
-    assert _decode_rc(g, sched) == sagms.EUNSUPPORTED
+    sched.schedule = 2
+    assert _decode_rc(g, sched) == sagms.EINVAL
+    # the layered schedule runs the min-sum family with FP32 messages only
+    assert _decode_rc(g, D("bp", schedule="layered")) == sagms.EUNSUPPORTED
+    assert _decode_rc(g, D("sagms", schedule="layered", precision="fp16")) == sagms.EUNSUPPORTED
+    assert _decode_rc(g, D("ms", schedule="layered", precision="int6")) == sagms.EUNSUPPORTED
     prec = D("ms")
     prec.msg_precision = 3
     assert _decode_rc(g, prec) == sagms.EUNSUPPORTED
