@@ -17,6 +17,7 @@ Modules
   philox    Philox4x32-10 counter-based generator (Salmon et al., SC'11)
   channel   depolarizing channel sampling, syndromes, bit packing, prior LLR
   decoders  MS / SMS / SAGMS / BP decoders (Alg. 1), FP64 and FP32 modes
+  layered   the layered (check-serial) schedule of the min-sum family
   judge     logical-failure judge (rank test and logical-operator test)
   stats     Wilson interval and log-ratio interval of an FER ratio
   analysis  transfer functions, BP-matching ratio, op-count model

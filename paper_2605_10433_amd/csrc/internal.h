@@ -79,8 +79,8 @@ struct GainKey {
 // cut into passes of at most `group` checks; a wavefront decodes 64 / group
 // frames, one per group of `group` lanes.  LDS words per wavefront: the
 // shared tables (pass table, variable pairs, gains, prior), then per frame
-// the posteriors (npad words), the c2v messages (m * dc) and the syndrome
-// and residual bits (2 * wm words each).
+// the posteriors (npad words), each check's outputs in compressed form (4
+// words per check) and the syndrome and residual bits (2 * wm words each).
 struct LayeredPlan {
     int dc = 0, group = 0, passes = 0, npad = 0, group_words = 0, table_words = 0;
     int32_t* pass_check = nullptr;   // device [passes][group], -1 = idle lane

@@ -8,10 +8,20 @@
 // per group of G lanes.  In pass p, lane q of a group updates check
 // pass_check[p][q] of its frame: it reads its variables' posteriors and its
 // own previous outputs from LDS, forms v2c = posterior - c2v_old, computes
-// the check output exactly as the flooding decoder does (cn_update), and
-// writes c2v_new and posterior = v2c + c2v_new back.  The checks of one pass
-// touch disjoint variables, and one wavefront's LDS operations complete in
-// order, so the passes need no barrier.  After the last pass every lane
+// the check output with the operations of the flooding decoder's check
+// update, and writes c2v_new and posterior = v2c + c2v_new back.  The checks
+// of one pass touch disjoint variables, and one wavefront's LDS operations
+// complete in order, so the passes need no barrier.
+//
+// A check's DC outputs are kept in three words instead of DC: S1 (the
+// output magnitude of the non-minimum edges with the parity sign), S1 xor S2
+// (S2: that of the minimum edges), and a mask holding, for edge k, bit k =
+// "|v2c_k| was the minimum" and bit 16 + k = the sign of v2c_k.  Output k is
+// S1 xor (D and minimum-bit-k) xor (sign-bit-k in the sign position), the
+// same 32 bits as when it was computed, so the messages stay exact while a
+// frame's LDS shrinks from n + m * DC to n + 4 m words and more frames fit
+// on a compute unit.  The tables of the next pass are read while the current
+// one computes.  After the last pass every lane
 // recomputes the residual-syndrome bits of the checks q, q + G, ... from the
 // hard decisions; the weight gives the next round's gains and the exit test.
 //
@@ -56,8 +66,8 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
     float* t_gain = reinterpret_cast<float*>(t_vars + m * (DC / 2));
     float* t_l0 = t_gain + 2 * (m + 1);
     float* post = reinterpret_cast<float*>(lds_u + la.tables + grp * la.gwords);
-    float* c2v = post + la.npad;
-    uint32_t* sbits = reinterpret_cast<uint32_t*>(c2v + m * DC);
+    uint4* cmp = reinterpret_cast<uint4*>(post + la.npad);  // per check: S1, S1 ^ S2, mask, unused
+    uint32_t* sbits = reinterpret_cast<uint32_t*>(cmp + m);
     uint32_t* rbits = sbits + 2 * wm;
 
     for (int t = lane; t < la.P * G; t += 64) t_pass[t] = (uint32_t)la.pass_check[t];
@@ -146,7 +156,7 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
             if (start) {
                 f = res;
                 for (int j = q; j < n; j += G) post[j] = t_l0[j];
-                for (int t = q; t < m * DC; t += G) c2v[t] = 0.0f;
+                for (int t = q; t < m; t += G) cmp[t] = make_uint4(0u, 0u, 0u, 0u);
                 if (q < wm) {
                     sbits[2 * q] = (uint32_t)res_word;
                     sbits[2 * q + 1] = (uint32_t)(res_word >> 32);
@@ -169,27 +179,57 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
 
         // one round: every layer of checks, pass by pass
         const float gs = t_gain[2 * w], gu = t_gain[2 * w + 1];
+        // (idle lanes, c = -1, read check 0's row and ignore it)
+        int c_next = (int)t_pass[q];
+        uint32_t pv_next[DC / 2];
+#pragma unroll
+        for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[max(c_next, 0) * (DC / 2) + k];
         for (int p = 0; p < la.P; ++p) {
-            const int c = (int)t_pass[p * G + q];
+            const int c = c_next;
+            uint32_t pv[DC / 2];
+#pragma unroll
+            for (int k = 0; k < DC / 2; ++k) pv[k] = pv_next[k];
+            if (p + 1 < la.P) {
+                c_next = (int)t_pass[(p + 1) * G + q];
+#pragma unroll
+                for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[max(c_next, 0) * (DC / 2) + k];
+            }
             if (active && c >= 0) {
                 uint32_t var[DC];
 #pragma unroll
                 for (int k = 0; k < DC / 2; ++k) {
-                    const uint32_t pv = t_vars[c * (DC / 2) + k];
-                    var[2 * k] = pv & 0xFFFFu;
-                    var[2 * k + 1] = pv >> 16;
+                    var[2 * k] = pv[k] & 0xFFFFu;
+                    var[2 * k + 1] = pv[k] >> 16;
                 }
-                float v[DC], out[DC];
-#pragma unroll
-                for (int k = 0; k < DC; ++k) v[k] = post[var[k]] - c2v[c * DC + k];
-                const uint32_t sb = ((sbits[c >> 5] >> (c & 31)) & 1u) << 31;
-                const bool unsat = (rbits[c >> 5] >> (c & 31)) & 1u;
-                cn_update<DC, false, SAGMS_MSG_FP32>(v, sb, unsat, gs, gu, out);
+                const uint4 old = cmp[c];
+                float v[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
-                    c2v[c * DC + k] = out[k];
-                    post[var[k]] = v[k] + out[k];
+                    const uint32_t minbit = (uint32_t)__builtin_amdgcn_sbfe(old.z, k, 1);
+                    const uint32_t prev = xor_and(old.x, old.y, minbit) ^ ((old.z << (15 - k)) & kSign);
+                    v[k] = post[var[k]] - __uint_as_float(prev);
                 }
+                const uint32_t par = xor_signs<DC>(v, ((sbits[c >> 5] >> (c & 31)) & 1u) << 31);
+                const bool unsat = (rbits[c >> 5] >> (c & 31)) & 1u;
+                const float alpha = unsat ? gu : gs;
+                float m1 = fabsf(v[0]), m2 = __builtin_inff();
+#pragma unroll
+                for (int k = 1; k < DC; ++k) {
+                    const float x = fabsf(v[k]);
+                    m2 = __builtin_amdgcn_fmed3f(m1, x, m2);
+                    m1 = fminf(m1, x);
+                }
+                const uint32_t S1 = or_and(bits(alpha * m1), par, kSign);
+                const uint32_t S2 = or_and(bits(alpha * m2), par, kSign);
+                uint32_t mask = 0;
+#pragma unroll
+                for (int k = 0; k < DC; ++k) {
+                    const bool is_min = fabsf(v[k]) == m1;
+                    const uint32_t out = xor_and(is_min ? S2 : S1, bits(v[k]), kSign);
+                    mask |= (is_min ? 1u << k : 0u) | ((bits(v[k]) >> 31) << (16 + k));
+                    post[var[k]] = v[k] + __uint_as_float(out);
+                }
+                cmp[c] = make_uint4(S1, S1 ^ S2, mask, 0u);
             }
         }
         const int w1 = residual(active);
