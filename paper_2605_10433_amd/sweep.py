@@ -13,7 +13,8 @@ setup's stopping rule) until --until-failures failures or --max-frames
 frames.  --p0 decodes with the prior of p0 instead of p (channel mismatch,
 Section V).  Decoders "sagms-derived" and "sagms-derived1.1" take their
 gains from Corollary 1 (alpha_max = alpha*(L0, d_c), alpha_min = 0.6
-alpha_max, eta = 1 / alpha_max or 1.1; sagms_derive_gains).  Prints one JSON
+alpha_max, eta = 1 / alpha_max or 1.1; sagms_derive_gains).  Decoders ending in "-layered" use
+the layered schedule (SAGMS_LAYERED).  Prints one JSON
 line per point (FER with its 95 % Wilson interval, mean and 99th-percentile
 round count, decode and end-to-end frames/s, and with --ratio-ref the FER
 ratio to that decoder with its 95 % log-method interval) and a markdown
@@ -45,6 +46,9 @@ DECODERS = {
     "sagms-derived": dict(derived=0.0),
     "sagms-derived1.1": dict(derived=1.1),
     "bp": dict(kind="bp"),
+    "ms-layered": dict(kind="ms", schedule="layered"),
+    "sms0.75-layered": dict(kind="sms", alpha=0.75, schedule="layered"),
+    "sagms-layered": dict(kind="sagms", alpha_min=0.30, alpha_max=0.50, eta=1.10, schedule="layered"),
 }
 CHUNK = 1 << 20
 
@@ -99,6 +103,7 @@ def run_point(g, code, p, stream_id, name, lmax, frames=None, until_failures=Non
         r["p0"] = p0
     if cfg.kind == sagms.KINDS["sagms"]:
         r["gains"] = [cfg.alpha_min, cfg.alpha_max, cfg.eta]
+    r["schedule"] = "layered" if cfg.schedule == sagms.SCHEDULES["layered"] else "flooding"
     return r
 
 
