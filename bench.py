@@ -557,6 +557,7 @@ def main():
     side = torch.cuda.Stream(device=dev) if args.pipeline else None
     sampled = [torch.cuda.Event() for _ in bufs]
     judged = [torch.cuda.Event() for _ in bufs]
+    decoded = [torch.cuda.Event() for _ in bufs]
 
     def sample(s):
         b = s % len(bufs)
@@ -583,8 +584,16 @@ def main():
         sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
         if ev is not None:
             ev[1].record(stream)
-        sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters)
-        judged[b].record(stream)
+        if side is None:
+            sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters)
+            judged[b].record(stream)
+        else:
+            # the judge runs on the second stream too, beside the next decode,
+            # so the decode stream runs decodes back to back
+            decoded[b].record(stream)
+            side.wait_event(decoded[b])
+            sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters, stream=side)
+            judged[b].record(side)
 
     for s in range(args.warmup):
         if side is not None and s == 0:
@@ -602,6 +611,8 @@ def main():
         sample(0)
     for s in range(args.steps):
         step(s, events[s], next_s=s + 1 if s + 1 < args.steps else None)
+    if side is not None:  # the last judge is part of the timed region
+        stream.wait_event(judged[(args.steps - 1) % len(bufs)])
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
