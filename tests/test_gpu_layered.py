@@ -148,6 +148,36 @@ def test_layered_full_size(dev):
     assert (buf["converged"].cpu().numpy()[pick].astype(bool) == r.converged).all()
 
 
+def test_layered_layer_wider_than_a_wavefront(dev):
+    """80 checks with disjoint supports (one layer, cut into passes of 64 and
+    16 checks) plus 10 checks across them (further layers), degree 6,
+    n = 480: against the oracle's layered FP32 mode."""
+    rng = np.random.default_rng(21)
+    m0, n = 80, 480
+    h = np.zeros((m0 + 10, n), dtype=np.uint8)
+    for i in range(m0):
+        h[i, 6 * i:6 * i + 6] = 1
+    for i in range(10):
+        blocks = rng.choice(m0, 6, replace=False)
+        h[m0 + i, 6 * blocks + rng.integers(0, 6, 6)] = 1
+    assert h.sum(axis=0).max() <= 3 and (h.sum(axis=1) == 6).all()
+    lay = layered.greedy_layers(h)
+    assert len(lay[0]) > 64 and len(lay) > 1
+    g = sagms.Graph.from_dense(h)
+    s = rng.integers(0, 2, (96, h.shape[0])).astype(np.uint8)
+    llr = rng.uniform(1.0, 4.0, n).astype(np.float32)
+    for kind, kw in KINDS:
+        prm = decoders.DecoderParams(kind=kind, lmax=30, **kw)
+        r = layered.decode_layered(decoders.TannerGraph(h), s, llr, prm, "fp32")
+        say("layered wide layer", kind)
+        e, it, cv, post = gpu_layered(g, s, llr, sagms.decoder_config(kind, lmax=30, schedule="layered", **kw), dev)
+        assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
+        ref = np.asarray(r.posterior, np.float32)
+        nan = np.isnan(ref)
+        assert (np.isnan(post) == nan).all()
+        assert (post.view(np.uint32)[~nan] == ref.view(np.uint32)[~nan]).all()
+
+
 def test_layered_refused_where_not_built(dev):
     g = sagms.Graph.gb(*workloads.code("G63"))
     synd = torch.zeros((4, g.words_m), dtype=torch.int64, device=dev)
