@@ -78,7 +78,8 @@ struct GainKey {
 // with disjoint supports (first fit in ascending check index), every layer
 // cut into passes of at most `group` checks; a wavefront decodes 64 / group
 // frames, one per group of `group` lanes.  LDS words per wavefront: the
-// shared tables (pass table, variable pairs, gains, prior), then per frame
+// shared tables (pass table, variable pairs, gains, prior, the prior's
+// residual bits), then per frame
 // the posteriors (npad words), each check's outputs in compressed form (4
 // words per check) and the syndrome and residual bits (2 * wm words each).
 struct LayeredPlan {

@@ -25,7 +25,8 @@
 // recomputes the residual-syndrome bits of the checks q, q + G, ... from the
 // hard decisions; the weight gives the next round's gains and the exit test.
 //
-// A wavefront owns a contiguous run of frames.  Each group holds one frame
+// A frame's first residual is its syndrome xor H [L0 < 0], the latter
+// computed once per wavefront.  A wavefront owns a contiguous run of frames.  Each group holds one frame
 // in decoding and one reserved next frame whose syndrome words are already
 // in flight; a group that finishes starts its reserved frame and reserves
 // the next unclaimed frame of the run, so groups stay busy until the run is
@@ -65,6 +66,7 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
     uint32_t* t_vars = t_pass + la.P * G;
     float* t_gain = reinterpret_cast<float*>(t_vars + m * (DC / 2));
     float* t_l0 = t_gain + 2 * (m + 1);
+    uint32_t* t_r0 = reinterpret_cast<uint32_t*>(t_l0 + n);  // residual bits of the prior's hard decision
     float* post = reinterpret_cast<float*>(lds_u + la.tables + grp * la.gwords);
     uint4* cmp = reinterpret_cast<uint4*>(post + la.npad);  // per check: S1, S1 ^ S2, mask, unused
     uint32_t* sbits = reinterpret_cast<uint32_t*>(cmp + m);
@@ -74,6 +76,23 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
     for (int t = lane; t < m * (DC / 2); t += 64) t_vars[t] = la.check_vars[t];
     for (int t = lane; t < 2 * (m + 1); t += 64) t_gain[t] = a.gains[t];
     for (int t = lane; t < n; t += 64) t_l0[t] = a.llr0[t] + 0.0f;  // -0 reads as +0
+    __syncthreads();
+    // H [L0 < 0] (mod 2): a frame's first residual is its syndrome xor this
+    for (int r = 0; r * 64 < m; ++r) {
+        const int c = r * 64 + lane;
+        uint32_t par = 0;
+        if (c < m)
+            for (int k = 0; k < DC / 2; ++k) {
+                const uint32_t pv = t_vars[c * (DC / 2) + k];
+                par ^= __float_as_uint(t_l0[pv & 0xFFFFu]) >> 31;
+                par ^= __float_as_uint(t_l0[pv >> 16]) >> 31;
+            }
+        const uint64_t bal = __ballot(par != 0);
+        if (lane == 0) {
+            t_r0[2 * r] = (uint32_t)bal;
+            t_r0[2 * r + 1] = (uint32_t)(bal >> 32);
+        }
+    }
     __syncthreads();
 
     const int64_t f_begin = (int64_t)blockIdx.x * la.frames_per_wave;
@@ -127,6 +146,7 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
     // Outputs of the group's frame (groups in `on`): hard decisions, rounds,
     // flag and, when asked for, the posteriors.
     auto finish = [&](bool on, int rounds, bool conv) {
+        if (__ballot(on) == 0) return;
         uint64_t word = 0;
         for (int r = 0; r * G < n; ++r) {
             const int j = r * G + q;
@@ -160,6 +180,8 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
                 if (q < wm) {
                     sbits[2 * q] = (uint32_t)res_word;
                     sbits[2 * q + 1] = (uint32_t)(res_word >> 32);
+                    rbits[2 * q] = (uint32_t)res_word ^ t_r0[2 * q];
+                    rbits[2 * q + 1] = (uint32_t)(res_word >> 32) ^ t_r0[2 * q + 1];
                 }
                 const int rank = __popcll(leaders & ((1ull << (grp * G)) - 1));
                 const int64_t claim = next + rank;
@@ -167,7 +189,9 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
                 if (res >= 0 && q < wm) res_word = a.synd[res * wm + q];
             }
             next += __popcll(leaders);
-            const int w0 = residual(start);
+            int w0 = 0;
+            if (start)
+                for (int t = 0; t < 2 * wm; ++t) w0 += __popc(rbits[t]);
             if (start) {
                 w = w0;
                 it = 0;

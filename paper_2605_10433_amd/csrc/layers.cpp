@@ -81,7 +81,7 @@ int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t
     // apart modulo the LDS banks keep those reads (and the 4-word reads of a
     // check's compressed outputs) on different banks
     plan->group_words = (plan->npad + 4 * m + 4 * g->wm + 63) / 64 * 64 + 4;
-    plan->table_words = round4(passes * group + m * (dc / 2) + 2 * (m + 1) + n);
+    plan->table_words = round4(passes * group + m * (dc / 2) + 2 * (m + 1) + n + 2 * g->wm);
     const int frames = 64 / group;
     if ((size_t)(plan->table_words + frames * plan->group_words) * 4 > (size_t)kLayeredMaxLds) {
         delete plan;
