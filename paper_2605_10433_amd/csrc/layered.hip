@@ -134,7 +134,9 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
                 } else if constexpr (G == 32) {
                     rbits[r] = (uint32_t)seg;
                 } else if constexpr (G == 16) {
-                    reinterpret_cast<uint16_t*>(rbits)[r] = (uint16_t)seg;
+                    // byte stores: they may alias the 32-bit reads of the bits
+                    reinterpret_cast<uint8_t*>(rbits)[2 * r] = (uint8_t)seg;
+                    reinterpret_cast<uint8_t*>(rbits)[2 * r + 1] = (uint8_t)(seg >> 8);
                 } else {
                     reinterpret_cast<uint8_t*>(rbits)[r] = (uint8_t)seg;
                 }
