@@ -320,10 +320,12 @@ def run_mix(args):
 
 
 def run_serve(args):
-    """The serving workload: the five-code batch throughput first (one tuned
-    sagms_batch_run over equal shares of 2^20 frames), then open-loop Poisson
-    traces at the offered loads, replayed in real time by the server; one
-    JSON line per load with p50 / p99 latency and served throughput."""
+    """The serving workload (FP16 messages by default): the five-code batch
+    throughput first (one tuned sagms_batch_run over equal shares of 2^20
+    frames, in the serving format and in FP32), then open-loop Poisson traces
+    at the offered loads (fractions of the serving-format batch throughput),
+    replayed in real time by the server; one JSON line per load with p50 /
+    p99 latency and served throughput beside the FP32 batch."""
     import torch
 
     import paper_2605_10433_amd as sagms
@@ -336,7 +338,8 @@ def run_serve(args):
                                **workloads.SAGMS_PARAMS)
     graphs = [sagms.Graph.gb(*workloads.code(n)) for n in workloads.SERVE_CODES]
 
-    # batch throughput of the same code mix (equal frame shares)
+    # batch throughput of the same code mix (equal frame shares), in the
+    # serving format (it sets the offered loads) and in FP32 (the comparison)
     share = (1 << 20) // len(graphs)
     segs = []
     for i, g in enumerate(graphs):
@@ -345,19 +348,29 @@ def run_serve(args):
                          buf["synd"])
         segs.append(dict(graph=g, synd=buf["synd"], ehat=buf["ehat"], iters=buf["iters"], converged=buf["converged"],
                          llr0=torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)))
-    batch = sagms.Batch(segs, cfg)
-    best, _ = batch.tune(reps=2)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    times = []
-    for _ in range(3):
-        e0.record()
-        batch.run()
-        e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    batch_ms = float(np.median(times))
+
+    def batch_time(c):
+        batch = sagms.Batch(segs, c)
+        plan, _ = batch.tune(reps=2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(3):
+            e0.record()
+            batch.run()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        batch.close()
+        return float(np.median(times)), plan
+
+    batch_ms, best = batch_time(cfg)
     batch_fps = share * len(graphs) / (batch_ms * 1e-3)
-    batch.close()
+    if args.precision == "fp32":
+        fp32_ms = batch_ms
+    else:
+        fp32_ms, _ = batch_time(sagms.decoder_config(args.decoder, lmax=workloads.SERVE_LMAX, alpha=args.alpha,
+                                                     **workloads.SAGMS_PARAMS))
+    fp32_fps = share * len(graphs) / (fp32_ms * 1e-3)
     del segs
 
     srv = sagms.Server(graphs, [np.full(g.n, sagms.prior_llr(p), dtype=np.float32) for g in graphs], cfg,
@@ -442,6 +455,8 @@ def run_serve(args):
             "served_frames_per_s": frames / span_s,
             "batch_frames_per_s": batch_fps,
             "batch_ms_2pow20": batch_ms,
+            "fp32_batch_frames_per_s": fp32_fps,
+            "fp32_batch_ms_2pow20": fp32_ms,
             "batch_plan": best.as_dict(),
             "requests": int(len(tr["reqs"])),
             "frames": frames,
@@ -477,7 +492,8 @@ def main():
                     help="serve: frames a class accumulates before it is launched while others run")
     ap.add_argument("--serve-max-wait-us", type=float, default=1000.0,
                     help="serve: longest wait before a class is launched anyway")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "int6"], help="message format (mix)")
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp16", "int6"],
+                    help="message format of the mix and serve workloads (default fp32 for the mix, fp16 for serving)")
     ap.add_argument("--plan", default="", help="mix: launch plan as JSON, e.g. '{\"kind\": \"tiered\"}'")
     ap.add_argument("--tune", action="store_true", help="mix: run the plan autotuner before timing")
     ap.add_argument("--graph-launch", action="store_true", help="mix: replay the batch as a HIP graph")
@@ -505,6 +521,8 @@ def main():
     args = ap.parse_args()
     if args.pipeline is None:
         args.pipeline = args.workload == "g63"
+    if args.precision is None:
+        args.precision = "fp16" if args.workload == "serve" else "fp32"
     if args.copy_calibration:
         copy_calibration()
         return
