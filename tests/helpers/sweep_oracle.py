@@ -22,24 +22,30 @@ def _graph():
 
 
 def decode_chunk(task):
-    """task = (kind, kw, p, frame0, nframes, lmax, arith).  Frames of seed 1,
-    stream = index of p in the sweep grid.  The prior is the FP32 value of
-    L0(p) in the "fp32" mode and the FP64 value in the "fp64" mode."""
+    """task = (kind, kw, p, frame0, nframes, lmax, arith[, schedule]).  Frames
+    of seed 1, stream = index of p in the sweep grid.  The prior is the FP32
+    value of L0(p) except in the "fp64" mode (FP64 value).  schedule:
+    "flooding" (default) or "layered"."""
     from threadpoolctl import threadpool_limits
 
     import workloads
-    from oracle import channel, decoders, judge
-    kind, kw, p, frame0, nf, lmax, arith = task
+    from oracle import channel, decoders, judge, layered
+    kind, kw, p, frame0, nf, lmax, arith = task[:7]
+    schedule = task[7] if len(task) > 7 else "flooding"
     g = _graph()
     with threadpool_limits(1):
         ex, _ = channel.sample_paulis(workloads.SWEEP_SEED, workloads.stream_of(p), frame0, nf, g["n"], p)
         s = channel.syndrome(g["hz"], ex)
         l0 = channel.prior_llr(p)
-        llr = np.full(g["n"], l0, dtype=np.float32 if arith == "fp32" else np.float64)
-        r = decoders.decode(g["tanner"], s, llr, decoders.DecoderParams(kind=kind, lmax=lmax, **kw), arith)
+        llr = np.full(g["n"], l0, dtype=np.float64 if arith == "fp64" else np.float32)
+        prm = decoders.DecoderParams(kind=kind, lmax=lmax, **kw)
+        if schedule == "layered":
+            r = layered.decode_layered(g["tanner"], s, llr, prm, arith)
+        else:
+            r = decoders.decode(g["tanner"], s, llr, prm, arith)
         fail = judge.judge_logical(g["lz"], ex, r.ehat, r.converged)
     out = dict(frame0=frame0, synd=channel.pack(s), ehat=channel.pack(r.ehat), iters=np.asarray(r.iters),
                converged=np.asarray(r.converged, dtype=bool), fail=np.asarray(fail, dtype=bool))
-    if arith == "fp32":
+    if arith != "fp64":
         out["posterior"] = np.asarray(r.posterior, dtype=np.float32)
     return out

@@ -13,6 +13,9 @@ syndromes, decoding, judge) and by the oracle in a pool of host processes.
 * SAGMS on all 2^20 frames of each point against the FP64 oracle: each FER
   lies in the other's 95 % Wilson interval, and frames that converge in
   both agree in their hard decision on >= 99 %.
+* SAGMS with FP16 and INT6 messages, and MS / SMS / SAGMS with the layered
+  schedule, on the first 2^16 frames of each point, frame by frame against
+  the oracle's matching mode.
 
 Several minutes of oracle time even on 16 host processes, so it runs only
 with SAGMS_SWEEP_PARITY=1 (workers: SAGMS_ORACLE_PROCS, default the host's
@@ -70,19 +73,19 @@ def g63(dev):
     return sagms.Graph.gb(*workloads.code("G63"))
 
 
-def oracle_run(pool, kind, kw, p, nframes, arith):
+def oracle_run(pool, kind, kw, p, nframes, arith, schedule="flooding"):
     import sweep_oracle   # tests/helpers, on the path the pool's workers inherit
-    tasks = [(kind, kw, p, f0, min(CHUNK, nframes - f0), LMAX, arith) for f0 in range(0, nframes, CHUNK)]
+    tasks = [(kind, kw, p, f0, min(CHUNK, nframes - f0), LMAX, arith, schedule) for f0 in range(0, nframes, CHUNK)]
     parts = sorted(pool.imap_unordered(sweep_oracle.decode_chunk, tasks), key=lambda r: r["frame0"])
     return {k: np.concatenate([r[k] for r in parts]) for k in parts[0] if k != "frame0"}
 
 
-def gpu_run(g, kind, kw, p, nframes, soft):
+def gpu_run(g, kind, kw, p, nframes, soft, **cfg_kw):
     buf = sagms.frame_buffers(g, nframes)
     sagms.gen_errors(g, workloads.SWEEP_SEED, workloads.stream_of(p), 0, nframes, p, buf["ex"], buf["ez"],
                      buf["synd"])
     llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device="cuda")
-    cfg = sagms.decoder_config(kind, lmax=LMAX, **kw)
+    cfg = sagms.decoder_config(kind, lmax=LMAX, **kw, **cfg_kw)
     post = torch.empty((nframes, g.n), dtype=torch.float32, device="cuda") if soft else None
     if soft:
         sagms.decode_soft(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"], post)
@@ -143,3 +146,45 @@ def test_sagms_fer_against_fp64_at_sweep_size(g63, pool, p):
         oracle_s=round(t_oracle, 1))
     assert lo_o <= f_gpu / FRAMES_FER <= hi_o and lo_g <= f_64 / FRAMES_FER <= hi_g
     assert differ[both].mean() < 0.01
+
+
+def same_frames(q, r):
+    """Frames whose decision, rounds, flag or any posterior bit differ
+    (posteriors that overflowed to NaN must be NaN on both sides)."""
+    nan = np.isnan(r["posterior"])
+    post_diff = (q["posterior"].view(np.uint32) != r["posterior"].view(np.uint32)) & ~nan
+    post_diff |= np.isnan(q["posterior"]) != nan
+    return int(((q["ehat"] != r["ehat"]).any(axis=1) | (q["iters"] != r["iters"]) |
+                (q["converged"] != r["converged"]) | post_diff.any(axis=1)).sum())
+
+
+@pytest.mark.parametrize("p", workloads.P_GRID)
+@pytest.mark.parametrize("precision", ["fp16", "int6"])
+def test_sweep_point_reduced_precision(g63, pool, precision, p):
+    """SAGMS with FP16 and INT6 messages on the first 2^16 frames of every
+    point, frame by frame against the oracle's matching mode."""
+    t0 = time.perf_counter()
+    r = oracle_run(pool, "sagms", workloads.SAGMS_PARAMS, p, FRAMES_EXACT, precision)
+    t_oracle = time.perf_counter() - t0
+    q = gpu_run(g63, "sagms", workloads.SAGMS_PARAMS, p, FRAMES_EXACT, soft=True, precision=precision)
+    assert (q["synd"] == r["synd"]).all()
+    bad = same_frames(q, r)
+    say("sagms-" + precision, p=p, frames=FRAMES_EXACT, mismatched_frames=bad, fer=float(q["fail"].mean()),
+        mean_iters=float(q["iters"].mean()), oracle_s=round(t_oracle, 1))
+    assert bad == 0 and (q["fail"] == r["fail"]).all()
+
+
+@pytest.mark.parametrize("p", workloads.P_GRID)
+@pytest.mark.parametrize("kind,kw", [("ms", {}), ("sms", dict(alpha=0.75)), ("sagms", dict(workloads.SAGMS_PARAMS))])
+def test_sweep_point_layered(g63, pool, kind, kw, p):
+    """The layered schedule on the first 2^16 frames of every point, frame by
+    frame against the oracle's layered FP32 mode."""
+    t0 = time.perf_counter()
+    r = oracle_run(pool, kind, kw, p, FRAMES_EXACT, "fp32", "layered")
+    t_oracle = time.perf_counter() - t0
+    q = gpu_run(g63, kind, kw, p, FRAMES_EXACT, soft=True, schedule="layered")
+    assert (q["synd"] == r["synd"]).all()
+    bad = same_frames(q, r)
+    say(kind + "-layered", kw=kw, p=p, frames=FRAMES_EXACT, mismatched_frames=bad, fer=float(q["fail"].mean()),
+        mean_iters=float(q["iters"].mean()), oracle_s=round(t_oracle, 1))
+    assert bad == 0 and (q["fail"] == r["fail"]).all()
