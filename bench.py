@@ -692,7 +692,7 @@ def main():
                                                             and args.schedule == "flooding") else None,
                      "kernel": kernel,
                      "ops_per_edge_update": OPS_PER_EDGE_UPDATE,
-                     "note": "decode launch time inside the pipelined steps (the next step's sampler shares the GPU)"
+                     "note": "decode launch time inside the pipelined steps (the next step's sampler and the previous step's judge share the GPU)"
                              if args.pipeline else "decode launch time, one stream",
                      "isolated": {"decode_ms": iso_ms, "achieved": iso_achieved, "frac": iso_achieved / VALU_PEAK_TOPS}},
     }
