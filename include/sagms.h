@@ -294,7 +294,8 @@ typedef struct {
 } sagms_tune_result;
 
 /* Creates a batch of nseg (1..16) segments for decoder cfg (MS, SMS or
- * SAGMS; BP is SAGMS_EUNSUPPORTED).  Checks every argument (SAGMS_EINVAL),
+ * SAGMS with the flooding schedule; BP or SAGMS_LAYERED is
+ * SAGMS_EUNSUPPORTED).  Checks every argument (SAGMS_EINVAL),
  * uploads the graphs' tables to the current device and synchronizes it.
  * The initial plan is SINGLE with tile_frames 8, waves_per_block 4,
  * blocks_per_cu 0 and reg_budget 0.  The batch keeps its own copy of cfg
@@ -388,7 +389,8 @@ typedef struct {
 } sagms_completion;
 
 /* Creates a server for ncodes (1..16) graphs with host prior vectors
- * llr0_host[c] (float [n_c], copied), decoder cfg (MS, SMS or SAGMS) and
+ * llr0_host[c] (float [n_c], copied), decoder cfg (MS, SMS or SAGMS, flooding
+ * schedule; SAGMS_EUNSUPPORTED otherwise) and
  * serving configuration scfg, on the current device.  Allocates its streams,
  * pinned staging and device buffers (in all: streams x max_frames_per_launch
  * frames of syndromes and outputs) and synchronizes the device. */

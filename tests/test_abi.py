@@ -175,6 +175,7 @@ def test_batch_create_checks_before_device_work():
     assert _create_rc(_segments([g], [-1]), 1, cfg) == sagms.EINVAL                    # negative frame count
     assert _create_rc(_segments([g], [4], null_buffers=True), 1, cfg) == sagms.EINVAL  # null buffers
     assert _create_rc(_segments([g], [4]), 1, sagms.decoder_config("bp")) == sagms.EUNSUPPORTED
+    assert _create_rc(_segments([g], [4]), 1, sagms.decoder_config("sagms", schedule="layered")) == sagms.EUNSUPPORTED
     assert _create_rc(_segments([g], [4]), 1, sagms.decoder_config("sagms", eta=0.5)) == sagms.EINVAL
     for name in ("sagms_batch_run", "sagms_batch_instantiate", "sagms_batch_destroy"):
         assert getattr(sagms.lib(), name)(None, *([None] if name == "sagms_batch_run" else [])) == sagms.EINVAL
@@ -219,6 +220,7 @@ def test_server_create_and_calls_check_before_device_work():
     assert rc(S(max_frames_per_launch=64, min_launch_frames=65, max_frames_in_flight=64)) == sagms.EINVAL
     assert rc(S(max_wait_us=-1.0)) == sagms.EINVAL
     assert rc(S(), c=sagms.decoder_config("bp")) == sagms.EUNSUPPORTED
+    assert rc(S(), c=sagms.decoder_config("sagms", schedule="layered")) == sagms.EUNSUPPORTED
     assert rc(S(), graphs=(ctypes.c_void_p * 1)(None)) == sagms.EINVAL
     assert rc(S(), priors=(ctypes.c_void_p * 1)(None)) == sagms.EINVAL
     assert L.sagms_server_submit(None, None, None) == sagms.EINVAL
