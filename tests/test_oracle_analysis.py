@@ -90,3 +90,19 @@ def test_log_ratio_interval():
     r, lo, hi = stats.log_ratio_interval(400, 10 ** 7, 500, 10 ** 7)
     assert lo < r < hi and r == pytest.approx(0.8)
     assert math.log(hi / r) == pytest.approx(math.log(r / lo))
+
+
+def test_log_ratio_interval_coverage():
+    """The interval's defining property, by simulation: over many pairs of
+    binomial samples with known FERs it covers the true ratio about 95 % of
+    the time, and its width shrinks as 1 / sqrt(failures)."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    for q1, q2, n in ((0.01, 0.02, 40_000), (0.2, 0.1, 4_000), (0.05, 0.05, 20_000)):
+        f1 = rng.binomial(n, q1, 4000)
+        f2 = rng.binomial(n, q2, 4000)
+        hit = [lo <= q1 / q2 <= hi for (_, lo, hi) in (stats.log_ratio_interval(a, n, b, n) for a, b in zip(f1, f2))]
+        assert 0.935 <= np.mean(hit) <= 0.965
+    w1 = stats.log_ratio_interval(100, 10 ** 6, 100, 10 ** 6)
+    w4 = stats.log_ratio_interval(400, 4 * 10 ** 6, 400, 4 * 10 ** 6)
+    assert math.log(w1[2] / w1[1]) == pytest.approx(2 * math.log(w4[2] / w4[1]), rel=1e-3)
