@@ -73,10 +73,10 @@ template <int DC, int CPL, int VPL>
 struct Lay {
     static constexpr int CW = 64 * CPL;
     static constexpr int ZERO = DC * CW;
-    static constexpr int POST0 = ZERO + 1;
+    static constexpr int POST0 = ZERO + 64;
     static constexpr int PADPOST = POST0 + 64 * VPL;
-    static constexpr int GAIN0 = (PADPOST + 2) & ~1;
-    static constexpr int WORDS = GAIN0 + 2 * (CW + 1);
+    static constexpr int GAIN0 = PADPOST + 64;
+    static constexpr int WORDS = GAIN0 + (CPL > 1 ? 2 * (CW + 1) : 0);
 };
 
 __device__ __forceinline__ uint32_t bits(float x) { return __float_as_uint(x); }
@@ -219,10 +219,8 @@ struct WaveDecoder {
         gu64 = a.gains[129];
         if constexpr (CPL > 1)
             for (int t = lane; t < 2 * (LY::CW + 1); t += 64) lds[LY::GAIN0 + t] = a.gains[t];
-        if (lane == 0) {
-            lds[LY::ZERO] = 0.0f;
-            lds[LY::PADPOST] = __builtin_inff();
-        }
+        lds[LY::ZERO + lane] = 0.0f;
+        lds[LY::PADPOST + lane] = __builtin_inff();
     }
 
     // Original syndrome bits of frame f for the lane's checks, at the sign

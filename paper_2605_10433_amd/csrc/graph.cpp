@@ -105,19 +105,43 @@ DecodeLayout make_layout(const DecodeShape& s) {
     DecodeLayout L;
     L.cw = 64 * s.cpl;
     L.zero = s.dc * L.cw;
-    L.post0 = L.zero + 1;
+    L.post0 = L.zero + 64;
     L.padpost = L.post0 + 64 * s.vpl;
-    L.gain0 = (L.padpost + 2) & ~1;  // 8-byte aligned pairs
-    L.words = L.gain0 + 2 * (L.cw + 1);
+    L.gain0 = L.padpost + 64;  // 8-byte aligned pairs
+    L.words = L.gain0 + (s.cpl > 1 ? 2 * (L.cw + 1) : 0);
     return L;
+}
+
+// The LDS serves a wavefront's 64 lanes as two halves of 32, each against
+// 32 banks of 4 bytes (measured: lanes 0-31 and 32-63 on the same banks
+// cost nothing, a stride of 2 words within a half costs a cycle).
+constexpr int kLdsBanks = 32;
+constexpr uint32_t kPadLane = 0xFFFFFFFFu;
+
+// Points the padding lanes (kPadLane) of each half of each 64-lane gather
+// of `table` at one word of the 64-word pool at `pool`: the word in the bank
+// that the real lanes of that half use least (one that none of them uses,
+// when there is one).  Lanes reading one word get it broadcast.
+static void place_padding(std::vector<uint32_t>& table, uint32_t pool) {
+    for (size_t half = 0; half < table.size(); half += 32) {
+        int load[kLdsBanks] = {};
+        for (int l = 0; l < 32; ++l)
+            if (table[half + l] != kPadLane) ++load[table[half + l] % kLdsBanks];
+        int best = 0;
+        for (int b = 1; b < kLdsBanks; ++b)
+            if (load[b] < load[best]) best = b;
+        const uint32_t word = pool + (uint32_t)((best - (int)(pool % kLdsBanks) + kLdsBanks) % kLdsBanks);
+        for (int l = 0; l < 32; ++l)
+            if (table[half + l] == kPadLane) table[half + l] = word;
+    }
 }
 
 // Builds the per-lane LDS address tables for the chosen shape.
 static void build_lane_tables(Graph* g) {
     const DecodeShape& s = g->shape;
     const DecodeLayout& L = g->layout;
-    g->cn_addr_host.assign((size_t)s.cpl * s.dc * 64, (uint32_t)L.padpost);
-    g->vn_addr_host.assign((size_t)s.vpl * s.dv * 64, (uint32_t)L.zero);
+    g->cn_addr_host.assign((size_t)s.cpl * s.dc * 64, kPadLane);
+    g->vn_addr_host.assign((size_t)s.vpl * s.dv * 64, kPadLane);
     for (int c = 0; c < g->m; ++c)
         for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p) {
             int j = g->cols[g->row_ptr[c] + p];
@@ -128,6 +152,8 @@ static void build_lane_tables(Graph* g) {
             int c = g->var_edges[j][r].first, p = g->var_edges[j][r].second;
             g->vn_addr_host[((size_t)(j / 64) * s.dv + r) * 64 + (j % 64)] = (uint32_t)(p * L.cw + c);
         }
+    place_padding(g->cn_addr_host, (uint32_t)L.padpost);
+    place_padding(g->vn_addr_host, (uint32_t)L.zero);
 }
 
 // Every variable's (check, position) pairs in posterior-sum order: ascending

@@ -57,11 +57,15 @@ int shape_index(const DecodeShape& s);
 
 // Per-wave LDS layout of the decode kernels, in 32-bit words:
 //   c2v slots  [dc][cw]   slot(c, p) = p * cw + c  (cw = 64 * cpl)
-//   zero       one word holding 0.0f (padding of short variables)
+//   zero       [64] words holding 0.0f (padding of short variables)
 //   posterior  [64 * vpl] posterior of variable j at post0 + j
-//   padpost    one word holding +inf (padding of short checks)
+//   padpost    [64] words holding +inf (padding of short checks)
 //   gains      [2 * (64 * cpl + 1)] pairs (gain satisfied, gain unsatisfied)
-//              indexed by the residual-syndrome weight w
+//              indexed by the residual-syndrome weight w; only when cpl > 1
+//              (one-block codes keep the table in registers)
+// The padding lanes of one half-wavefront of an LDS gather all read one word
+// of a padding pool, chosen in a bank that the half's other lanes leave free,
+// so that padding adds no bank conflict.
 struct DecodeLayout {
     int cw, zero, post0, padpost, gain0, words;
 };
