@@ -110,18 +110,29 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
 
     // Residual bits of the group's frame from its posteriors; returns the
     // weight.  Executed by the lanes of the groups in `on`.
+    // (the variable pairs of the next row of checks are read one row ahead;
+    // lanes past the last check read the last check's row and ignore it)
     auto residual = [&](bool on) -> int {
         int weight = 0;
+        uint32_t pv_next[DC / 2];
+#pragma unroll
+        for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[min(q, m - 1) * (DC / 2) + k];
         for (int r = 0; r * G < m; ++r) {
             const int c = r * G + q;
+            uint32_t pv[DC / 2];
+#pragma unroll
+            for (int k = 0; k < DC / 2; ++k) pv[k] = pv_next[k];
+            if ((r + 1) * G < m) {
+#pragma unroll
+                for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[min(c + G, m - 1) * (DC / 2) + k];
+            }
             bool bit = false;
             if (on && c < m) {
                 uint32_t par = (sbits[c >> 5] >> (c & 31)) & 1u;
 #pragma unroll
                 for (int k = 0; k < DC / 2; ++k) {
-                    const uint32_t pv = t_vars[c * (DC / 2) + k];
-                    par ^= __float_as_uint(post[pv & 0xFFFFu]) >> 31;
-                    par ^= __float_as_uint(post[pv >> 16]) >> 31;
+                    par ^= __float_as_uint(post[pv[k] & 0xFFFFu]) >> 31;
+                    par ^= __float_as_uint(post[pv[k] >> 16]) >> 31;
                 }
                 bit = par != 0;
             }
@@ -205,20 +216,24 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
 
         // one round: every layer of checks, pass by pass
         const float gs = t_gain[2 * w], gu = t_gain[2 * w + 1];
-        // (idle lanes, c = -1, read check 0's row and ignore it)
-        int c_next = (int)t_pass[q];
+        // The tables are read ahead: during pass p the check of pass p + 2
+        // and the variable pairs of pass p + 1's check, so that no table
+        // read waits on another.  (Idle lanes, c = -1, read check 0's row and
+        // ignore it.)
+        int c_next = la.P > 1 ? (int)t_pass[G + q] : -1;
         uint32_t pv_next[DC / 2];
+        int c = (int)t_pass[q];
 #pragma unroll
-        for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[max(c_next, 0) * (DC / 2) + k];
+        for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[max(c, 0) * (DC / 2) + k];
         for (int p = 0; p < la.P; ++p) {
-            const int c = c_next;
             uint32_t pv[DC / 2];
 #pragma unroll
             for (int k = 0; k < DC / 2; ++k) pv[k] = pv_next[k];
+            int c_after = -1;
             if (p + 1 < la.P) {
-                c_next = (int)t_pass[(p + 1) * G + q];
 #pragma unroll
                 for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[max(c_next, 0) * (DC / 2) + k];
+                if (p + 2 < la.P) c_after = (int)t_pass[(p + 2) * G + q];
             }
             if (active && c >= 0) {
                 uint32_t var[DC];
@@ -227,13 +242,19 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
                     var[2 * k] = pv[k] & 0xFFFFu;
                     var[2 * k + 1] = pv[k] >> 16;
                 }
+                // issue every LDS read of the check before the first use, so
+                // that their latencies overlap
                 const uint4 old = cmp[c];
+                float pj[DC];
+#pragma unroll
+                for (int k = 0; k < DC; ++k) pj[k] = post[var[k]];
+                __builtin_amdgcn_sched_barrier(0);
                 float v[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     const uint32_t minbit = (uint32_t)__builtin_amdgcn_sbfe(old.z, k, 1);
                     const uint32_t prev = xor_and(old.x, old.y, minbit) ^ ((old.z << (15 - k)) & kSign);
-                    v[k] = post[var[k]] - __uint_as_float(prev);
+                    v[k] = pj[k] - __uint_as_float(prev);
                 }
                 const uint32_t par = xor_signs<DC>(v, ((sbits[c >> 5] >> (c & 31)) & 1u) << 31);
                 const bool unsat = (rbits[c >> 5] >> (c & 31)) & 1u;
@@ -257,6 +278,8 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
                 }
                 cmp[c] = make_uint4(S1, S1 ^ S2, mask, 0u);
             }
+            c = c_next;
+            c_next = c_after;
         }
         const int w1 = residual(active);
         bool done = false;
