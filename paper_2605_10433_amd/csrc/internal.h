@@ -86,8 +86,13 @@ struct GainKey {
 // residual bits), then per frame
 // the posteriors (npad words), each check's outputs in compressed form (4
 // words per check) and the syndrome and residual bits (2 * wm words each).
+// Schedules of at most this many passes keep each lane's check outputs in
+// registers (layered.hip); longer ones keep them in LDS.
+constexpr int kLayeredRegPasses = 16;
+
 struct LayeredPlan {
     int dc = 0, group = 0, passes = 0, npad = 0, group_words = 0, table_words = 0;
+    bool regs = false;  // check outputs in registers (passes <= kLayeredRegPasses)
     int32_t* pass_check = nullptr;   // device [passes][group], -1 = idle lane
     uint32_t* check_vars = nullptr;  // device [m][dc / 2] variable pairs
 };

@@ -20,10 +20,14 @@
 // S1 xor (D and minimum-bit-k) xor (sign-bit-k in the sign position), the
 // same 32 bits as when it was computed, so the messages stay exact while a
 // frame's LDS shrinks from n + m * DC to n + 4 m words and more frames fit
-// on a compute unit.  The tables of the next pass are read while the current
-// one computes.  After the last pass every lane
-// recomputes the residual-syndrome bits of the checks q, q + G, ... from the
-// hard decisions; the weight gives the next round's gains and the exit test.
+// on a compute unit.  When the schedule has at most kLayeredRegPasses passes
+// (PMAX > 0), lane q keeps the three words of its check of every pass in
+// registers instead (the pass loop is unrolled, so each pass names its own
+// registers) and a frame needs only its posteriors and syndrome bits in LDS.
+// The tables of the next passes are read while the current one computes.
+// After the last pass every lane recomputes the residual-syndrome bits of the
+// checks q, q + G, ... from the hard decisions; the weight gives the next
+// round's gains and the exit test.
 //
 // A frame's first residual is its syndrome xor H [L0 < 0], the latter
 // computed once per wavefront.  A wavefront owns a contiguous run of frames.  Each group holds one frame
@@ -52,10 +56,15 @@ __device__ __forceinline__ uint64_t group_segment(uint64_t ballot, int grp) {
     }
 }
 
-template <int DC, int G>
-__global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
+// PMAX = 0: check outputs in LDS; PMAX > 0: in registers, at most PMAX passes
+// (register budget: 4 wavefronts per SIMD, 3 for degree 10, whose 16 passes
+// of outputs and wider check update do not fit 128 VGPRs).
+template <int DC, int G, int PMAX>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PMAX > 0 ? (DC >= 10 ? 3 : 4) : 1)))
+layered_kernel(LayeredArgs la) {
     constexpr int F = 64 / G;
     static_assert(F * G == 64, "G must divide 64");
+    constexpr int NREG = PMAX > 0 ? PMAX : 1;
     extern __shared__ uint32_t lds_u[];
     const DecodeArgs& a = la.a;
     const int lane = threadIdx.x;
@@ -68,8 +77,8 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
     float* t_l0 = t_gain + 2 * (m + 1);
     uint32_t* t_r0 = reinterpret_cast<uint32_t*>(t_l0 + n);  // residual bits of the prior's hard decision
     float* post = reinterpret_cast<float*>(lds_u + la.tables + grp * la.gwords);
-    uint4* cmp = reinterpret_cast<uint4*>(post + la.npad);  // per check: S1, S1 ^ S2, mask, unused
-    uint32_t* sbits = reinterpret_cast<uint32_t*>(cmp + m);
+    uint4* cmp = reinterpret_cast<uint4*>(post + la.npad);  // PMAX = 0, per check: S1, S1 ^ S2, mask, unused
+    uint32_t* sbits = PMAX > 0 ? reinterpret_cast<uint32_t*>(post + la.npad) : reinterpret_cast<uint32_t*>(cmp + m);
     uint32_t* rbits = sbits + 2 * wm;
 
     for (int t = lane; t < la.P * G; t += 64) t_pass[t] = (uint32_t)la.pass_check[t];
@@ -107,6 +116,10 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
     if (res >= 0 && q < wm) res_word = a.synd[res * wm + q];
     int it = 0, w = 0;
     bool active = false;
+    // PMAX > 0: outputs of the lane's check in pass p (S1, S1 ^ S2, mask)
+    uint32_t rs1[NREG], rd[NREG], rmk[NREG];
+#pragma unroll
+    for (int p = 0; p < NREG; ++p) rs1[p] = rd[p] = rmk[p] = 0u;
 
     // Residual bits of the group's frame from its posteriors; returns the
     // weight.  Executed by the lanes of the groups in `on`.
@@ -189,7 +202,12 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
             if (start) {
                 f = res;
                 for (int j = q; j < n; j += G) post[j] = t_l0[j];
-                for (int t = q; t < m; t += G) cmp[t] = make_uint4(0u, 0u, 0u, 0u);
+                if constexpr (PMAX > 0) {
+#pragma unroll
+                    for (int p = 0; p < PMAX; ++p) rs1[p] = rd[p] = rmk[p] = 0u;
+                } else {
+                    for (int t = q; t < m; t += G) cmp[t] = make_uint4(0u, 0u, 0u, 0u);
+                }
                 if (q < wm) {
                     sbits[2 * q] = (uint32_t)res_word;
                     sbits[2 * q + 1] = (uint32_t)(res_word >> 32);
@@ -216,6 +234,54 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
 
         // one round: every layer of checks, pass by pass
         const float gs = t_gain[2 * w], gu = t_gain[2 * w + 1];
+        // Check update of check c (variable pairs pv) in place of its
+        // previous outputs (s1, dd, mk): reads its posteriors, writes the
+        // new posteriors and returns the new outputs in (s1, dd, mk).
+        auto check_update = [&](int c, const uint32_t (&pv)[DC / 2], uint32_t& s1, uint32_t& dd, uint32_t& mk) {
+            uint32_t var[DC];
+#pragma unroll
+            for (int k = 0; k < DC / 2; ++k) {
+                var[2 * k] = pv[k] & 0xFFFFu;
+                var[2 * k + 1] = pv[k] >> 16;
+            }
+            // issue every LDS read of the check before the first use, so that
+            // their latencies overlap
+            float pj[DC];
+#pragma unroll
+            for (int k = 0; k < DC; ++k) pj[k] = post[var[k]];
+            const uint32_t sword = sbits[c >> 5], rword = rbits[c >> 5];
+            __builtin_amdgcn_sched_barrier(0);
+            float v[DC];
+#pragma unroll
+            for (int k = 0; k < DC; ++k) {
+                const uint32_t minbit = (uint32_t)__builtin_amdgcn_sbfe(mk, k, 1);
+                const uint32_t prev = xor_and(s1, dd, minbit) ^ ((mk << (15 - k)) & kSign);
+                v[k] = pj[k] - __uint_as_float(prev);
+            }
+            const uint32_t par = xor_signs<DC>(v, ((sword >> (c & 31)) & 1u) << 31);
+            const bool unsat = (rword >> (c & 31)) & 1u;
+            const float alpha = unsat ? gu : gs;
+            float m1 = fabsf(v[0]), m2 = __builtin_inff();
+#pragma unroll
+            for (int k = 1; k < DC; ++k) {
+                const float x = fabsf(v[k]);
+                m2 = __builtin_amdgcn_fmed3f(m1, x, m2);
+                m1 = fminf(m1, x);
+            }
+            const uint32_t S1 = or_and(bits(alpha * m1), par, kSign);
+            const uint32_t S2 = or_and(bits(alpha * m2), par, kSign);
+            uint32_t mask = 0;
+#pragma unroll
+            for (int k = 0; k < DC; ++k) {
+                const bool is_min = fabsf(v[k]) == m1;
+                const uint32_t out = xor_and(is_min ? S2 : S1, bits(v[k]), kSign);
+                mask |= (is_min ? 1u << k : 0u) | ((bits(v[k]) >> 31) << (16 + k));
+                post[var[k]] = v[k] + __uint_as_float(out);
+            }
+            s1 = S1;
+            dd = S1 ^ S2;
+            mk = mask;
+        };
         // The tables are read ahead: during pass p the check of pass p + 2
         // and the variable pairs of pass p + 1's check, so that no table
         // read waits on another.  (Idle lanes, c = -1, read check 0's row and
@@ -225,8 +291,7 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
         int c = (int)t_pass[q];
 #pragma unroll
         for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[max(c, 0) * (DC / 2) + k];
-        for (int p = 0; p < la.P; ++p) {
-            uint32_t pv[DC / 2];
+        auto read_ahead = [&](int p, uint32_t (&pv)[DC / 2]) -> int {
 #pragma unroll
             for (int k = 0; k < DC / 2; ++k) pv[k] = pv_next[k];
             int c_after = -1;
@@ -235,51 +300,32 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
                 for (int k = 0; k < DC / 2; ++k) pv_next[k] = t_vars[max(c_next, 0) * (DC / 2) + k];
                 if (p + 2 < la.P) c_after = (int)t_pass[(p + 2) * G + q];
             }
-            if (active && c >= 0) {
-                uint32_t var[DC];
+            return c_after;
+        };
+        if constexpr (PMAX > 0) {
 #pragma unroll
-                for (int k = 0; k < DC / 2; ++k) {
-                    var[2 * k] = pv[k] & 0xFFFFu;
-                    var[2 * k + 1] = pv[k] >> 16;
+            for (int p = 0; p < PMAX; ++p) {
+                if (p < la.P) {
+                    uint32_t pv[DC / 2];
+                    const int c_after = read_ahead(p, pv);
+                    if (active && c >= 0) check_update(c, pv, rs1[p], rd[p], rmk[p]);
+                    c = c_next;
+                    c_next = c_after;
                 }
-                // issue every LDS read of the check before the first use, so
-                // that their latencies overlap
-                const uint4 old = cmp[c];
-                float pj[DC];
-#pragma unroll
-                for (int k = 0; k < DC; ++k) pj[k] = post[var[k]];
-                __builtin_amdgcn_sched_barrier(0);
-                float v[DC];
-#pragma unroll
-                for (int k = 0; k < DC; ++k) {
-                    const uint32_t minbit = (uint32_t)__builtin_amdgcn_sbfe(old.z, k, 1);
-                    const uint32_t prev = xor_and(old.x, old.y, minbit) ^ ((old.z << (15 - k)) & kSign);
-                    v[k] = pj[k] - __uint_as_float(prev);
-                }
-                const uint32_t par = xor_signs<DC>(v, ((sbits[c >> 5] >> (c & 31)) & 1u) << 31);
-                const bool unsat = (rbits[c >> 5] >> (c & 31)) & 1u;
-                const float alpha = unsat ? gu : gs;
-                float m1 = fabsf(v[0]), m2 = __builtin_inff();
-#pragma unroll
-                for (int k = 1; k < DC; ++k) {
-                    const float x = fabsf(v[k]);
-                    m2 = __builtin_amdgcn_fmed3f(m1, x, m2);
-                    m1 = fminf(m1, x);
-                }
-                const uint32_t S1 = or_and(bits(alpha * m1), par, kSign);
-                const uint32_t S2 = or_and(bits(alpha * m2), par, kSign);
-                uint32_t mask = 0;
-#pragma unroll
-                for (int k = 0; k < DC; ++k) {
-                    const bool is_min = fabsf(v[k]) == m1;
-                    const uint32_t out = xor_and(is_min ? S2 : S1, bits(v[k]), kSign);
-                    mask |= (is_min ? 1u << k : 0u) | ((bits(v[k]) >> 31) << (16 + k));
-                    post[var[k]] = v[k] + __uint_as_float(out);
-                }
-                cmp[c] = make_uint4(S1, S1 ^ S2, mask, 0u);
             }
-            c = c_next;
-            c_next = c_after;
+        } else {
+            for (int p = 0; p < la.P; ++p) {
+                uint32_t pv[DC / 2];
+                const int c_after = read_ahead(p, pv);
+                if (active && c >= 0) {
+                    const uint4 old = cmp[c];
+                    uint32_t s1 = old.x, dd = old.y, mk = old.z;
+                    check_update(c, pv, s1, dd, mk);
+                    cmp[c] = make_uint4(s1, dd, mk, 0u);
+                }
+                c = c_next;
+                c_next = c_after;
+            }
         }
         const int w1 = residual(active);
         bool done = false;
@@ -295,9 +341,9 @@ __global__ void __launch_bounds__(64) layered_kernel(LayeredArgs la) {
 
 namespace {
 
-template <int DC, int G>
+template <int DC, int G, int PMAX>
 int launch_dg(const LayeredArgs& la, size_t lds, int num_cu, hipStream_t st) {
-    const void* fn = reinterpret_cast<const void*>(&layered_kernel<DC, G>);
+    const void* fn = reinterpret_cast<const void*>(&layered_kernel<DC, G, PMAX>);
     int per_cu = 0;
     SAGMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds));
     if (per_cu < 1) return fail(SAGMS_EUNSUPPORTED, "layered kernel does not fit a compute unit");
@@ -307,20 +353,25 @@ int launch_dg(const LayeredArgs& la, size_t lds, int num_cu, hipStream_t st) {
     LayeredArgs x = la;
     x.frames_per_wave = (la.a.nframes + waves - 1) / waves;
     waves = (la.a.nframes + x.frames_per_wave - 1) / x.frames_per_wave;
-    hipLaunchKernelGGL((layered_kernel<DC, G>), dim3((unsigned)waves), dim3(64), lds, st, x);
+    hipLaunchKernelGGL((layered_kernel<DC, G, PMAX>), dim3((unsigned)waves), dim3(64), lds, st, x);
     SAGMS_HIP(hipGetLastError());
     return SAGMS_OK;
 }
 
-template <int DC>
-int launch_d(int G, const LayeredArgs& la, size_t lds, int num_cu, hipStream_t st) {
+template <int DC, int PMAX>
+int launch_dp(int G, const LayeredArgs& la, size_t lds, int num_cu, hipStream_t st) {
     switch (G) {
-        case 8: return launch_dg<DC, 8>(la, lds, num_cu, st);
-        case 16: return launch_dg<DC, 16>(la, lds, num_cu, st);
-        case 32: return launch_dg<DC, 32>(la, lds, num_cu, st);
-        case 64: return launch_dg<DC, 64>(la, lds, num_cu, st);
+        case 8: return launch_dg<DC, 8, PMAX>(la, lds, num_cu, st);
+        case 16: return launch_dg<DC, 16, PMAX>(la, lds, num_cu, st);
+        case 32: return launch_dg<DC, 32, PMAX>(la, lds, num_cu, st);
+        case 64: return launch_dg<DC, 64, PMAX>(la, lds, num_cu, st);
         default: return fail(SAGMS_EUNSUPPORTED, "layered group size %d (internal)", G);
     }
+}
+
+template <int DC>
+int launch_d(int G, bool regs, const LayeredArgs& la, size_t lds, int num_cu, hipStream_t st) {
+    return regs ? launch_dp<DC, kLayeredRegPasses>(G, la, lds, num_cu, st) : launch_dp<DC, 0>(G, la, lds, num_cu, st);
 }
 
 }  // namespace
@@ -341,9 +392,9 @@ int launch_layered(const LayeredPlan& plan, const DecodeArgs& a, hipStream_t st)
     SAGMS_HIP(hipGetDevice(&dev));
     SAGMS_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
     switch (plan.dc) {
-        case 6: return launch_d<6>(plan.group, la, lds, num_cu, st);
-        case 8: return launch_d<8>(plan.group, la, lds, num_cu, st);
-        case 10: return launch_d<10>(plan.group, la, lds, num_cu, st);
+        case 6: return launch_d<6>(plan.group, plan.regs, la, lds, num_cu, st);
+        case 8: return launch_d<8>(plan.group, plan.regs, la, lds, num_cu, st);
+        case 10: return launch_d<10>(plan.group, plan.regs, la, lds, num_cu, st);
         default: return fail(SAGMS_EUNSUPPORTED, "layered schedule: check degree %d not compiled", plan.dc);
     }
 }

@@ -76,11 +76,17 @@ int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t
     plan->group = group;
     plan->passes = passes;
     plan->npad = round4(n);
+    plan->regs = passes <= kLayeredRegPasses;
     // every group of a wavefront updates the same check in the same pass, so
-    // its lanes read the same offsets of their own slices: slices 4 words
-    // apart modulo the LDS banks keep those reads (and the 4-word reads of a
-    // check's compressed outputs) on different banks
-    plan->group_words = (plan->npad + 4 * m + 4 * g->wm + 63) / 64 * 64 + 4;
+    // its lanes read the same offsets of their own slices.  With the check
+    // outputs in LDS, slices 4 words apart modulo the LDS banks keep those
+    // reads (and the 4-word reads of a check's compressed outputs) on
+    // different banks; with them in registers, the 32 / G groups of a
+    // half-wavefront (32 banks) sit G words apart modulo 32.
+    if (plan->regs)
+        plan->group_words = (plan->npad + 4 * g->wm + 31) / 32 * 32 + (group < 32 ? group : 0);
+    else
+        plan->group_words = (plan->npad + 4 * m + 4 * g->wm + 63) / 64 * 64 + 4;
     plan->table_words = round4(passes * group + m * (dc / 2) + 2 * (m + 1) + n + 2 * g->wm);
     const int frames = 64 / group;
     if ((size_t)(plan->table_words + frames * plan->group_words) * 4 > (size_t)kLayeredMaxLds) {
