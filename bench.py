@@ -41,13 +41,13 @@ OPS_PER_EDGE_UPDATE = 8
 # while the kernel source is unchanged since the counters were taken.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_g63_sagms_p005_traffic.json")
 DECODE_SOURCES = [os.path.join(ROOT, "paper_2605_10433_amd", "csrc", f)
-                  for f in ("decode.hip", "decode_core.h", "schedule.h", "internal.h", "graph.cpp")]
+                  for f in ("decode.hip", "decode_core.h", "schedule.h", "internal.h", "graph.cpp", "lds_pad.h")]
 
 
 def decode_source_sha256():
     """SHA-256 of the decode kernel's sources (decode.hip, decode_core.h,
-    schedule.h, and internal.h and graph.cpp, which fix its LDS layout and
-    address tables; in that order)."""
+    schedule.h, and internal.h, graph.cpp and lds_pad.h, which fix its LDS
+    layout and address tables; in that order)."""
     import hashlib
     h = hashlib.sha256()
     for f in DECODE_SOURCES:

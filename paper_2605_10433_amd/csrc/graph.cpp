@@ -8,6 +8,7 @@
 #include <new>
 
 #include "internal.h"
+#include "lds_pad.h"
 
 namespace sagms {
 
@@ -110,30 +111,6 @@ DecodeLayout make_layout(const DecodeShape& s) {
     L.gain0 = L.padpost + 64;  // 8-byte aligned pairs
     L.words = L.gain0 + (s.cpl > 1 ? 2 * (L.cw + 1) : 0);
     return L;
-}
-
-// The LDS serves a wavefront's 64 lanes as two halves of 32, each against
-// 32 banks of 4 bytes (measured: lanes 0-31 and 32-63 on the same banks
-// cost nothing, a stride of 2 words within a half costs a cycle).
-constexpr int kLdsBanks = 32;
-constexpr uint32_t kPadLane = 0xFFFFFFFFu;
-
-// Points the padding lanes (kPadLane) of each half of each 64-lane gather
-// of `table` at one word of the 64-word pool at `pool`: the word in the bank
-// that the real lanes of that half use least (one that none of them uses,
-// when there is one).  Lanes reading one word get it broadcast.
-static void place_padding(std::vector<uint32_t>& table, uint32_t pool) {
-    for (size_t half = 0; half < table.size(); half += 32) {
-        int load[kLdsBanks] = {};
-        for (int l = 0; l < 32; ++l)
-            if (table[half + l] != kPadLane) ++load[table[half + l] % kLdsBanks];
-        int best = 0;
-        for (int b = 1; b < kLdsBanks; ++b)
-            if (load[b] < load[best]) best = b;
-        const uint32_t word = pool + (uint32_t)((best - (int)(pool % kLdsBanks) + kLdsBanks) % kLdsBanks);
-        for (int l = 0; l < 32; ++l)
-            if (table[half + l] == kPadLane) table[half + l] = word;
-    }
 }
 
 // Builds the per-lane LDS address tables for the chosen shape.

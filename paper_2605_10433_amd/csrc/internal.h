@@ -65,7 +65,7 @@ int shape_index(const DecodeShape& s);
 //              (one-block codes keep the table in registers)
 // The padding lanes of one half-wavefront of an LDS gather all read one word
 // of a padding pool, chosen in a bank that the half's other lanes leave free,
-// so that padding adds no bank conflict.
+// so that padding adds no bank conflict (place_padding, lds_pad.h).
 struct DecodeLayout {
     int cw, zero, post0, padpost, gain0, words;
 };
