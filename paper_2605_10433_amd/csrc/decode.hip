@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
     const int64_t f_begin = ws.frame0[k] + (wave - ws.wave0[k]) * ws.chunk[k];
     const int64_t f_end = min(f_begin + (int64_t)ws.chunk[k], ws.frame0[k + 1]);
     if (f_begin >= f_end) return;
-    using WD = WaveDecoder<DC, DV, CPL, VPL, BP, MT>;
+    using WD = WaveDecoder<DC, DV, CPL, VPL, BP, MT, CPL == 1>;
     WD d;
     d.load(a, lds, lane);
     uint64_t word[CPL];

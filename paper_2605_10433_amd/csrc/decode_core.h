@@ -190,8 +190,16 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, boo
 // One wave's decoder for one code: graph tables, priors and gains held in
 // registers, loaded once (load) and reused for every frame (frame).  The LDS
 // slice `lds` belongs to this wave alone.
-template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
+//
+// The round's two gains come from the gain table, indexed by the residual
+// weight w: GV (one-block codes only) reads the pair with one vector load at
+// the wave-uniform index, which costs no VALU work beyond the select and
+// whose latency hides behind the running minima when many wavefronts share
+// a SIMD (the stand-alone decode kernel); otherwise lane w holds entry w in
+// registers (one-block codes, two lane reads) or the table sits in LDS.
+template <int DC, int DV, int CPL, int VPL, bool BP, int MT, bool GV = false>
 struct WaveDecoder {
+    static_assert(!GV || CPL == 1, "vector-load gains are for one-block codes");
     using LY = Lay<DC, CPL, VPL>;
     uint32_t caddr[CPL][DC];
     uint32_t vaddr[VPL][DV];
@@ -213,10 +221,12 @@ struct WaveDecoder {
             L0[k] = j < a.n ? prior<MT>(a.llr0[j]) : __builtin_inff();
         }
         // gain table: in registers (lane w holds entry w) when m <= 64, else in LDS
-        gsl = a.gains[2 * lane];
-        gul = a.gains[2 * lane + 1];
-        gs64 = a.gains[128];
-        gu64 = a.gains[129];
+        if constexpr (!GV) {
+            gsl = a.gains[2 * lane];
+            gul = a.gains[2 * lane + 1];
+            gs64 = a.gains[128];
+            gu64 = a.gains[129];
+        }
         if constexpr (CPL > 1)
             for (int t = lane; t < 2 * (LY::CW + 1); t += 64) lds[LY::GAIN0 + t] = a.gains[t];
         lds[LY::ZERO + lane] = 0.0f;
@@ -283,7 +293,11 @@ struct WaveDecoder {
             ++it;
             // CN update; gains of the residual weight w (eq. (alphaeff))
             float gs, gu;
-            if constexpr (CPL == 1) {
+            if constexpr (GV) {
+                const float2 gg = reinterpret_cast<const float2*>(a.gains)[w];
+                gs = gg.x;
+                gu = gg.y;
+            } else if constexpr (CPL == 1) {
                 gs = w < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gsl), w)) : gs64;
                 gu = w < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gul), w)) : gu64;
             } else {

@@ -147,7 +147,7 @@ DecodeLayout make_layout(const DecodeShape& s);
 struct DecodeArgs {
     const uint64_t* synd;
     const float* llr0;
-    const float* gains;
+    const float* gains;  // [cw + 1] pairs (gain of a satisfied, of an unsatisfied check) by residual weight
     const uint32_t* cn_addr;
     const uint32_t* vn_addr;
     uint64_t* ehat;
