@@ -94,7 +94,7 @@ struct LayeredPlan {
     int dc = 0, group = 0, passes = 0, npad = 0, group_words = 0, table_words = 0;
     bool regs = false;  // check outputs in registers (passes <= kLayeredRegPasses)
     int32_t* pass_check = nullptr;   // device [passes][group], -1 = idle lane
-    uint32_t* check_vars = nullptr;  // device [m][dc / 2] variable pairs
+    uint32_t* check_vars = nullptr;  // device [m][dc / 2] variable pairs as 16-bit byte offsets 4 j
 };
 
 struct DeviceTables {

@@ -42,10 +42,15 @@ namespace sagms {
 struct LayeredArgs {
     DecodeArgs a;
     const int32_t* pass_check;   // [P][G] check of (pass, lane), -1 = idle
-    const uint32_t* check_vars;  // [m][DC / 2] variable pairs (low, high 16 bits)
+    const uint32_t* check_vars;  // [m][DC / 2] variable pairs as byte offsets 4 j (low, high 16 bits)
     int64_t frames_per_wave;
     int P, npad, gwords, tables;  // tables: LDS words in front of the group slices
 };
+
+// The float at byte offset `off` of `base` (LDS tables hold byte offsets).
+__device__ __forceinline__ float& at(float* base, uint32_t off) {
+    return *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off);
+}
 
 template <int G>
 __device__ __forceinline__ uint64_t group_segment(uint64_t ballot, int grp) {
@@ -93,8 +98,8 @@ layered_kernel(LayeredArgs la) {
         if (c < m)
             for (int k = 0; k < DC / 2; ++k) {
                 const uint32_t pv = t_vars[c * (DC / 2) + k];
-                par ^= __float_as_uint(t_l0[pv & 0xFFFFu]) >> 31;
-                par ^= __float_as_uint(t_l0[pv >> 16]) >> 31;
+                par ^= __float_as_uint(at(t_l0, pv & 0xFFFFu)) >> 31;
+                par ^= __float_as_uint(at(t_l0, pv >> 16)) >> 31;
             }
         const uint64_t bal = __ballot(par != 0);
         if (lane == 0) {
@@ -144,8 +149,8 @@ layered_kernel(LayeredArgs la) {
                 uint32_t par = (sbits[c >> 5] >> (c & 31)) & 1u;
 #pragma unroll
                 for (int k = 0; k < DC / 2; ++k) {
-                    par ^= __float_as_uint(post[pv[k] & 0xFFFFu]) >> 31;
-                    par ^= __float_as_uint(post[pv[k] >> 16]) >> 31;
+                    par ^= __float_as_uint(at(post, pv[k] & 0xFFFFu)) >> 31;
+                    par ^= __float_as_uint(at(post, pv[k] >> 16)) >> 31;
                 }
                 bit = par != 0;
             }
@@ -238,17 +243,19 @@ layered_kernel(LayeredArgs la) {
         // previous outputs (s1, dd, mk): reads its posteriors, writes the
         // new posteriors and returns the new outputs in (s1, dd, mk).
         auto check_update = [&](int c, const uint32_t (&pv)[DC / 2], uint32_t& s1, uint32_t& dd, uint32_t& mk) {
-            uint32_t var[DC];
+            // byte offsets of the check's posteriors (the 16-bit halves fold
+            // into the address adds)
+            uint32_t off[DC];
 #pragma unroll
             for (int k = 0; k < DC / 2; ++k) {
-                var[2 * k] = pv[k] & 0xFFFFu;
-                var[2 * k + 1] = pv[k] >> 16;
+                off[2 * k] = pv[k] & 0xFFFFu;
+                off[2 * k + 1] = pv[k] >> 16;
             }
             // issue every LDS read of the check before the first use, so that
             // their latencies overlap
             float pj[DC];
 #pragma unroll
-            for (int k = 0; k < DC; ++k) pj[k] = post[var[k]];
+            for (int k = 0; k < DC; ++k) pj[k] = at(post, off[k]);
             const uint32_t sword = sbits[c >> 5], rword = rbits[c >> 5];
             __builtin_amdgcn_sched_barrier(0);
             float v[DC];
@@ -276,7 +283,7 @@ layered_kernel(LayeredArgs la) {
                 const bool is_min = fabsf(v[k]) == m1;
                 const uint32_t out = xor_and(is_min ? S2 : S1, bits(v[k]), kSign);
                 mask |= (is_min ? 1u << k : 0u) | ((bits(v[k]) >> 31) << (16 + k));
-                post[var[k]] = v[k] + __uint_as_float(out);
+                at(post, off[k]) = v[k] + __uint_as_float(out);
             }
             s1 = S1;
             dd = S1 ^ S2;

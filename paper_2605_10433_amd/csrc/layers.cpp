@@ -29,7 +29,8 @@ int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t
             return fail(SAGMS_EUNSUPPORTED, "layered schedule: needs every check of the same degree");
     if (dc != 6 && dc != 8 && dc != 10)
         return fail(SAGMS_EUNSUPPORTED, "layered schedule: check degree %d not compiled (6, 8 or 10)", dc);
-    if (n > 0xFFFF) return fail(SAGMS_EUNSUPPORTED, "layered schedule: n must be < 65536");
+    // variables are held as 16-bit byte offsets (4 j)
+    if (n > 0x3FFF) return fail(SAGMS_EUNSUPPORTED, "layered schedule: n must be < 16384");
 
     // first-fit layers
     std::vector<std::vector<int>> layers;
@@ -68,8 +69,8 @@ int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t
     std::vector<uint32_t> check_vars((size_t)m * (dc / 2));
     for (int c = 0; c < m; ++c)
         for (int k = 0; k < dc / 2; ++k)
-            check_vars[(size_t)c * (dc / 2) + k] =
-                (uint32_t)g->cols[g->row_ptr[c] + 2 * k] | ((uint32_t)g->cols[g->row_ptr[c] + 2 * k + 1] << 16);
+            check_vars[(size_t)c * (dc / 2) + k] = (uint32_t)(4 * g->cols[g->row_ptr[c] + 2 * k]) |
+                                                   ((uint32_t)(4 * g->cols[g->row_ptr[c] + 2 * k + 1]) << 16);
 
     auto* plan = new LayeredPlan();
     plan->dc = dc;
