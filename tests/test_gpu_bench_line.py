@@ -1,0 +1,42 @@
+"""The bench's result line on the GPU: a short run of bench.py (two timed
+steps of the l = 63 workload) prints one JSON line with the fields its
+readers rely on: the metric and its unit, the timed steps, one GPU, the
+configuration, and the roofline object of the decode kernel."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_prints_one_complete_line():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("bench line: 2 steps, 2 warm-up steps", flush=True)
+    r = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "2", "--warmup", "2",
+                        "--no-cpu-baseline"], capture_output=True, text=True, timeout=240, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+                "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert key in out, key
+    assert out["n_gpus"] == 1 and out["steps"] == 2 and out["warmup"] == 2
+    assert out["value"] > 0 and out["ms_per_step"] > 0 and out["higher_is_better"] is True
+    assert out["unit"] == "frames/s" and out["dtype"] == "f32" and out["data"] == "synthetic"
+    assert "workload" in out["config"] and out["config"]["frames_per_step"] == 1 << 20
+    rl = out["roofline"]
+    for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert key in rl, key
+    assert rl["bound"] == "alu" and rl["unit"] == "TOP/s"
+    assert 0 < rl["frac"] <= 1 and rl["frac"] == pytest.approx(rl["achieved"] / rl["peak"], rel=1e-9)
+    # the whole step takes at least as long as its decode
+    assert out["decode_ms_per_step"] <= out["ms_per_step"]
