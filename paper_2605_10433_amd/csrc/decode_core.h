@@ -172,8 +172,13 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, boo
         // from folding the select back into one product per edge.
         uint32_t S1, S2;
         if constexpr (MT == SAGMS_MSG_FP32) {
-            S1 = or_and(bits(alpha * m1), par, kSign);
-            S2 = or_and(bits(alpha * m2), par, kSign);
+            // the gain carries the parity sign: m1, m2 >= 0 and a product's
+            // sign is the xor of its operands' signs while its magnitude
+            // rounds the same either way, so these are the bits of alpha m1
+            // and alpha m2 with the parity sign attached
+            const float sa = __uint_as_float(xor_and(bits(alpha), par, kSign));
+            S1 = bits(sa * m1);
+            S2 = bits(sa * m2);
         } else {
             S1 = or_and(bits(quantize<MT>(alpha * quantize<MT>(m1))), par, kSign);
             S2 = or_and(bits(quantize<MT>(alpha * quantize<MT>(m2))), par, kSign);
