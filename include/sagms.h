@@ -23,8 +23,13 @@
  *     as void* (NULL = the null stream).  Every device call is asynchronous
  *     on `stream` and never synchronises.  Host pointers are named *_host.
  *   - A graph handle is immutable after it is built and may be shared by
- *     calls on several streams at once.  Its device tables are created on
- *     the first device call per HIP device (one-off hipMalloc + copy).
+ *     calls on several streams at once.  Its device tables are copied to the
+ *     current HIP device when it is built (if the process has a device), and
+ *     to another device by sagms_graph_upload.  The device calls
+ *     (sagms_gen_errors, sagms_decode, sagms_decode_soft, sagms_judge)
+ *     allocate nothing, copy nothing and never synchronise: they only launch
+ *     kernels, so they may be captured into a HIP graph, first call
+ *     included.  Decoder gains are evaluated inside the kernels.
  */
 #ifndef SAGMS_H
 #define SAGMS_H
@@ -167,6 +172,15 @@ int sagms_graph_logicals(sagms_graph g, uint64_t* rows_host);
 
 int sagms_destroy_graph(sagms_graph g);
 
+/* Copies the graph's device tables (edge and LDS address tables, packed
+ * rows, logical basis, layered schedule tables; a few KB) to the current HIP
+ * device, once: later calls on that device return SAGMS_OK at once.  The
+ * graph builders already do this for the device current when they run.
+ * Synchronous (hipMalloc + hipMemcpy); not for use under stream capture.
+ * The device calls return SAGMS_EINVAL on a device without the tables.
+ * The copies are freed by sagms_destroy_graph. */
+int sagms_graph_upload(sagms_graph g);
+
 /* Binary prior LLR of the X part of a depolarizing error of strength p:
  * ln((1 - 2p/3) / (2p/3)) (the binary marginal of the prior of Section II),
  * rounded to float.  Returns NaN for p outside (0, 0.75). */
@@ -202,7 +216,8 @@ int sagms_gen_errors(sagms_graph g, uint64_t seed, uint32_t stream_id, uint64_t 
                      double p, uint64_t* ex, uint64_t* ez, uint64_t* synd, void* stream);
 
 /* Decode nframes syndromes (Algorithm 1, flooding schedule).
- *   synd      device [nframes][words_m] packed syndromes s
+ *   synd      device [nframes][words_m] packed syndromes s (bits at or above
+ *             m in the last word of a frame are ignored)
  *   llr0      device [n] float prior LLRs L0_j (finite; -0.0 reads as +0.0)
  *   ehat      device [nframes][words_n] packed hard decisions e_hat
  *   iters     device [nframes] number of CN update rounds performed:

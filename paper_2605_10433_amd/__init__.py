@@ -95,6 +95,7 @@ def lib():
             "sagms_graph_rows": [vp, vp],
             "sagms_graph_logicals": [vp, vp],
             "sagms_destroy_graph": [vp],
+            "sagms_graph_upload": [vp],
             "sagms_gen_errors": [vp, u64, u32, u64, i64, dbl, vp, vp, vp, vp],
             "sagms_decode": [vp, vp, vp, vp, i64, vp, vp, vp, vp],
             "sagms_decode_soft": [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp],
@@ -218,6 +219,11 @@ class Graph:
         out = np.zeros((max(self.k, 0), self.words_n), dtype=np.uint64)
         _check(lib().sagms_graph_logicals(self._h, out.ctypes.data))
         return out
+
+    def upload(self):
+        """Copies the device tables to the current HIP device (the builders
+        already do so for the device current when they run)."""
+        _check(lib().sagms_graph_upload(self._h))
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -40,19 +40,19 @@ int check_cfg(const sagms_decoder_cfg* c) {
     return SAGMS_OK;
 }
 
-int cfg_gains(Graph* g, DeviceTables* t, const sagms_decoder_cfg* cfg, const float** out, hipStream_t st) {
-    GainKey key{cfg->kind, 0.0, 0.0, 0.0, 0.0};
-    if (cfg->kind == SAGMS_SMS) key.a = cfg->alpha;
+GainLaw gain_law(const sagms_decoder_cfg* cfg) {
+    GainLaw law{cfg->kind, 0, 0.0, 0.0, 0.0, 0.0};
+    if (cfg->kind == SAGMS_SMS) law.a = cfg->alpha;
     if (cfg->kind == SAGMS_SAGMS) {
-        key.amin = cfg->alpha_min;
-        key.amax = cfg->alpha_max;
-        key.eta = cfg->eta;
+        law.amin = cfg->alpha_min;
+        law.amax = cfg->alpha_max;
+        law.eta = cfg->eta;
     }
-    if (cfg->kind == SAGMS_BP) key.kind = SAGMS_MS;  // BP ignores the gains
-    return gain_table(g, t, key, out, st);
+    if (cfg->kind == SAGMS_BP) law.kind = SAGMS_MS;  // BP ignores the gains
+    return law;
 }
 
-DecodeArgs decode_args(const Graph* g, const DeviceTables* t, const float* gains, const uint64_t* synd,
+DecodeArgs decode_args(const Graph* g, const DeviceTables* t, const GainLaw& gains, const uint64_t* synd,
                        const float* llr0, int64_t nframes, uint64_t* ehat, int32_t* iters, uint8_t* converged,
                        float* posterior, int lmax, int frames_per_wave) {
     DecodeArgs a{};
@@ -90,7 +90,7 @@ int sagms_gen_errors(sagms_graph gh, uint64_t seed, uint32_t stream_id, uint64_t
     if (!ex || !synd) return fail(SAGMS_EINVAL, "ex and synd must not be null");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     DeviceTables* t = nullptr;
-    int rc = device_tables(g, &t, st);
+    int rc = device_tables(g, &t);
     if (rc) return rc;
     SampleArgs a{};
     a.cols = t->cols;
@@ -133,20 +133,14 @@ int sagms_decode_soft(sagms_graph gh, const uint64_t* synd, const float* llr0, c
     if (nframes == 0) return SAGMS_OK;
     if (!synd || !llr0 || !ehat || !iters || !converged) return fail(SAGMS_EINVAL, "null buffer");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (cfg->schedule == SAGMS_LAYERED && g->layered.status != SAGMS_OK)
+        return fail(g->layered.status, "%s", g->layered.why.c_str());
     DeviceTables* t = nullptr;
-    rc = device_tables(g, &t, st);
+    rc = device_tables(g, &t);
     if (rc) return rc;
-    const float* gains = nullptr;
-    rc = cfg_gains(g, t, cfg, &gains, st);
-    if (rc) return rc;
-    const DecodeArgs a = decode_args(g, t, gains, synd, llr0, nframes, ehat, iters, converged, posterior, cfg->lmax,
-                                     cfg->frames_per_wave);
-    if (cfg->schedule == SAGMS_LAYERED) {
-        const LayeredPlan* plan = nullptr;
-        rc = layered_plan(g, t, &plan, st);
-        if (rc) return rc;
-        return launch_layered(*plan, a, st);
-    }
+    const DecodeArgs a = decode_args(g, t, gain_law(cfg), synd, llr0, nframes, ehat, iters, converged, posterior,
+                                     cfg->lmax, cfg->frames_per_wave);
+    if (cfg->schedule == SAGMS_LAYERED) return launch_layered(t->layered, a, st);
     return launch_decode(g->shape, cfg->kind == SAGMS_BP, cfg->msg_precision, a, st);
 }
 
@@ -160,7 +154,7 @@ int sagms_judge(sagms_graph gh, const uint64_t* ex, const uint64_t* ehat, const 
     if (!ex || !ehat || !converged || !iters || !counters) return fail(SAGMS_EINVAL, "null buffer");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     DeviceTables* t = nullptr;
-    int rc = device_tables(g, &t, st);
+    int rc = device_tables(g, &t);
     if (rc) return rc;
     JudgeArgs a{};
     a.ex = ex;

@@ -212,15 +212,13 @@ int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_deco
         const sagms_segment& x = segs[s];
         Graph* g = reinterpret_cast<Graph*>(x.graph);
         DeviceTables* t = nullptr;
-        const float* gains = nullptr;
-        rc = device_tables(g, &t, nullptr);
-        if (!rc) rc = cfg_gains(g, t, cfg, &gains, nullptr);
+        rc = upload_tables(g, &t);
         if (rc) {
             destroy(b);
             return rc;
         }
         MixedSegment ms{};
-        ms.a = decode_args(g, t, gains, x.synd, x.llr0, x.nframes, x.ehat, x.iters, x.converged, x.posterior,
+        ms.a = decode_args(g, t, gain_law(cfg), x.synd, x.llr0, x.nframes, x.ehat, x.iters, x.converged, x.posterior,
                            cfg->lmax, 0);
         ms.shape = shape_index(g->shape);
         b->segs.push_back(ms);
@@ -228,7 +226,7 @@ int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_deco
         b->shape.push_back(g->shape);
     }
     e = hipMalloc(&b->d_queues, sizeof(uint32_t) * kNumMixedTiers * kMaxQueues * kQueueStride);
-    if (e == hipSuccess) e = hipDeviceSynchronize();  // gain tables uploaded on the null stream
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         destroy(b);
         return hip_fail(e, "batch set-up");

@@ -15,8 +15,9 @@ namespace sagms {
 constexpr int kWavesPerBlock = 4;
 constexpr int kTaperLevels = 2;  // waves per tail level of the tapered schedule, in resident waves
 
+// kg: the gain pairs of one-block codes (CPL == 1); unused otherwise.
 template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
-__global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs a, WaveSchedule ws) {
+__global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs a, WaveSchedule ws, KernelGains kg) {
     using LY = Lay<DC, CPL, VPL>;
     extern __shared__ float lds_all[];
     const int lane = threadIdx.x & 63;
@@ -38,7 +39,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
     uint32_t sb[CPL];
     WD::load_syndrome(a, f_begin, word);
     WD::syndrome_bits(a, lane, word, sb);
-    for (int64_t f = f_begin; f < f_end; ++f) d.frame(a, lds, lane, f, sb, f + 1 < f_end ? f + 1 : f);
+    for (int64_t f = f_begin; f < f_end; ++f) d.frame(a, lds, lane, f, sb, f + 1 < f_end ? f + 1 : f, &kg);
 }
 
 // Waves per block: up to kWavesPerBlock, as many as fit in 64 KiB of LDS.
@@ -47,9 +48,26 @@ static int waves_per_block(const DecodeLayout& L) {
     return w < 1 ? 1 : (w > kWavesPerBlock ? kWavesPerBlock : w);
 }
 
+// Host evaluation of the gain law, operation for operation as gain_pair.
+static float2 host_gain_pair(const GainLaw& law, int w, int m) {
+    double gs = 1.0, gu = 1.0;
+    if (law.kind == SAGMS_SMS) {
+        gs = gu = law.a;
+    } else if (law.kind == SAGMS_SAGMS) {
+        const double gamma = (double)w / (double)m;
+        const double g = law.amax - (law.amax - law.amin) * gamma;
+        gs = g;
+        gu = g * law.eta;
+    }
+    return make_float2((float)gs, (float)gu);
+}
+
 template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
 static void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const DecodeArgs& a, const WaveSchedule& ws) {
-    hipLaunchKernelGGL((decode_kernel<DC, DV, CPL, VPL, BP, MT>), grid, block, lds, st, a, ws);
+    KernelGains kg{};
+    if constexpr (CPL == 1)
+        for (int w = 0; w <= 64; ++w) kg.g[w] = host_gain_pair(a.gains, w, a.m);
+    hipLaunchKernelGGL((decode_kernel<DC, DV, CPL, VPL, BP, MT>), grid, block, lds, st, a, ws, kg);
 }
 
 // Waves of one kernel resident on the current device at once (occupancy of

@@ -76,8 +76,40 @@ struct Lay {
     static constexpr int POST0 = ZERO + 64;
     static constexpr int PADPOST = POST0 + 64 * VPL;
     static constexpr int GAIN0 = PADPOST + 64;
-    static constexpr int WORDS = GAIN0 + (CPL > 1 ? 2 * (CW + 1) : 0);
+    static constexpr int WORDS = GAIN0 + 2 * (CW + 1);
 };
+
+// Gains of a satisfied and of an unsatisfied check at residual weight w out
+// of m checks (eq. (alphaeff)): 1 for MS and BP, alpha for SMS, and for SAGMS
+// g = alpha_max - (alpha_max - alpha_min) * (w / m) and g * eta.  Evaluated
+// in IEEE double one rounded operation at a time (the library is compiled
+// without contraction, and double division is correctly rounded), then
+// rounded to float: the values a host evaluates from the same formula.
+__device__ __forceinline__ float2 gain_pair(const GainLaw& law, int w, int m) {
+    double gs = 1.0, gu = 1.0;
+    if (law.kind == SAGMS_SMS) {
+        gs = gu = law.a;
+    } else if (law.kind == SAGMS_SAGMS) {
+        const double gamma = (double)w / (double)m;
+        const double g = law.amax - (law.amax - law.amin) * gamma;
+        gs = g;
+        gu = g * law.eta;
+    }
+    return make_float2((float)gs, (float)gu);
+}
+
+// Gain pairs of residual weights 0 .. 64, passed by value as a kernel
+// argument by the stand-alone decode kernel of one-block codes (m <= 64):
+// the round's pair is then one scalar load at a wave-uniform offset.
+struct KernelGains {
+    float2 g[65];
+};
+
+// Writes the gain pairs of residual weights 0 .. entries - 1 to the wave's
+// LDS at gain0 (pairs of floats, 8-byte aligned).
+__device__ __forceinline__ void write_gains(const GainLaw& law, int m, int entries, float* gain0, int lane) {
+    for (int w = lane; w < entries; w += 64) reinterpret_cast<float2*>(gain0)[w] = gain_pair(law, w, m);
+}
 
 __device__ __forceinline__ uint32_t bits(float x) { return __float_as_uint(x); }
 
@@ -192,24 +224,22 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, boo
     }
 }
 
-// One wave's decoder for one code: graph tables, priors and gains held in
+// One wave's decoder for one code: graph tables and priors held in
 // registers, loaded once (load) and reused for every frame (frame).  The LDS
 // slice `lds` belongs to this wave alone.
 //
-// The round's two gains come from the gain table, indexed by the residual
-// weight w: GV (one-block codes only) reads the pair with one vector load at
-// the wave-uniform index, which costs no VALU work beyond the select and
-// whose latency hides behind the running minima when many wavefronts share
-// a SIMD (the stand-alone decode kernel); otherwise lane w holds entry w in
-// registers (one-block codes, two lane reads) or the table sits in LDS.
-template <int DC, int DV, int CPL, int VPL, bool BP, int MT, bool GV = false>
+// The round's two gains are indexed by the residual weight w.  KG: from the
+// kernel argument table (KernelGains, one-block codes), by a scalar load;
+// otherwise from the gain table that load() writes to the wave's LDS slice,
+// by one 8-byte read at a wave-uniform address (a broadcast, no bank
+// conflict).  Either latency hides behind the running minima.
+template <int DC, int DV, int CPL, int VPL, bool BP, int MT, bool KG = false>
 struct WaveDecoder {
-    static_assert(!GV || CPL == 1, "vector-load gains are for one-block codes");
+    static_assert(!KG || CPL == 1, "kernel-argument gains are for one-block codes");
     using LY = Lay<DC, CPL, VPL>;
     uint32_t caddr[CPL][DC];
     uint32_t vaddr[VPL][DV];
     float L0[VPL];
-    float gsl, gul, gs64, gu64;
 
     __device__ __forceinline__ void load(const DecodeArgs& a, float* lds, int lane) {
 #pragma unroll
@@ -225,15 +255,7 @@ struct WaveDecoder {
             int j = k * 64 + lane;
             L0[k] = j < a.n ? prior<MT>(a.llr0[j]) : __builtin_inff();
         }
-        // gain table: in registers (lane w holds entry w) when m <= 64, else in LDS
-        if constexpr (!GV) {
-            gsl = a.gains[2 * lane];
-            gul = a.gains[2 * lane + 1];
-            gs64 = a.gains[128];
-            gu64 = a.gains[129];
-        }
-        if constexpr (CPL > 1)
-            for (int t = lane; t < 2 * (LY::CW + 1); t += 64) lds[LY::GAIN0 + t] = a.gains[t];
+        if constexpr (!KG) write_gains(a.gains, a.m, LY::CW + 1, lds + LY::GAIN0, lane);
         lds[LY::ZERO + lane] = 0.0f;
         lds[LY::PADPOST + lane] = __builtin_inff();
     }
@@ -256,7 +278,7 @@ struct WaveDecoder {
     // The syndrome of frame f_next is loaded when the frame starts and left
     // in sb when its rounds are done, so the load latency hides behind them.
     __device__ __forceinline__ void frame(const DecodeArgs& a, float* lds, int lane, int64_t f, uint32_t (&sb)[CPL],
-                                          int64_t f_next) {
+                                          int64_t f_next, const KernelGains* kg = nullptr) {
         uint64_t next_word[CPL];
         load_syndrome(a, f_next, next_word);
         float post[VPL];
@@ -297,19 +319,12 @@ struct WaveDecoder {
             if (it == a.lmax) break;
             ++it;
             // CN update; gains of the residual weight w (eq. (alphaeff))
-            float gs, gu;
-            if constexpr (GV) {
-                const float2 gg = reinterpret_cast<const float2*>(a.gains)[w];
-                gs = gg.x;
-                gu = gg.y;
-            } else if constexpr (CPL == 1) {
-                gs = w < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gsl), w)) : gs64;
-                gu = w < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gul), w)) : gu64;
-            } else {
-                const float2 gg = *reinterpret_cast<const float2*>(&lds[LY::GAIN0 + 2 * w]);
-                gs = gg.x;
-                gu = gg.y;
-            }
+            float2 gg;
+            if constexpr (KG)
+                gg = kg->g[w];
+            else
+                gg = *reinterpret_cast<const float2*>(&lds[LY::GAIN0 + 2 * w]);
+            const float gs = gg.x, gu = gg.y;
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
                 cn_update<DC, BP, MT>(v[k], sb[k], unsat[k], gs, gu, c2v[k]);

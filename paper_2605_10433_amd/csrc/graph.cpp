@@ -109,7 +109,7 @@ DecodeLayout make_layout(const DecodeShape& s) {
     L.post0 = L.zero + 64;
     L.padpost = L.post0 + 64 * s.vpl;
     L.gain0 = L.padpost + 64;  // 8-byte aligned pairs
-    L.words = L.gain0 + (s.cpl > 1 ? 2 * (L.cw + 1) : 0);
+    L.words = L.gain0 + 2 * (L.cw + 1);
     return L;
 }
 
@@ -253,83 +253,108 @@ static int build(int32_t m, int32_t n, const std::vector<int>& rp, const std::ve
         delete g;
         return rc;
     }
+    plan_layers(g);
+    // tables on the current device, if the process has one (host-only use
+    // needs none: the device calls report a graph without tables)
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+        DeviceTables* t = nullptr;
+        rc = upload_tables(g, &t);
+        if (rc != SAGMS_OK) {
+            const std::string why = g_last_error;
+            (void)sagms_destroy_graph(reinterpret_cast<sagms_graph>(g));
+            g_last_error = why;
+            return rc;
+        }
+    } else {
+        (void)hipGetLastError();
+    }
     *out = reinterpret_cast<sagms_graph>(g);
     return SAGMS_OK;
 }
 
 // ---- per-device tables ------------------------------------------------
-int device_tables(Graph* g, DeviceTables** out, hipStream_t stream) {
+static int upload_locked(Graph* g, DeviceTables* t) {
+    size_t ncols = (size_t)g->m * std::max(g->dc_max, 1);
+    std::vector<int32_t> cols(ncols, -1);
+    for (int c = 0; c < g->m; ++c)
+        for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p)
+            cols[(size_t)c * std::max(g->dc_max, 1) + p] = g->cols[g->row_ptr[c] + p];
+    SAGMS_HIP(hipMalloc(&t->cols, std::max<size_t>(ncols, 1) * sizeof(int32_t)));
+    SAGMS_HIP(hipMemcpy(t->cols, cols.data(), ncols * sizeof(int32_t), hipMemcpyHostToDevice));
+    SAGMS_HIP(hipMalloc(&t->rows, g->rows_bits.size() * sizeof(uint64_t)));
+    SAGMS_HIP(hipMemcpy(t->rows, g->rows_bits.data(), g->rows_bits.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    if (g->shape_ok) {
+        SAGMS_HIP(hipMalloc(&t->cn_addr, g->cn_addr_host.size() * sizeof(uint32_t)));
+        SAGMS_HIP(hipMemcpy(t->cn_addr, g->cn_addr_host.data(), g->cn_addr_host.size() * sizeof(uint32_t),
+                            hipMemcpyHostToDevice));
+        SAGMS_HIP(hipMalloc(&t->vn_addr, g->vn_addr_host.size() * sizeof(uint32_t)));
+        SAGMS_HIP(hipMemcpy(t->vn_addr, g->vn_addr_host.data(), g->vn_addr_host.size() * sizeof(uint32_t),
+                            hipMemcpyHostToDevice));
+    }
+    if (g->k > 0) {
+        SAGMS_HIP(hipMalloc(&t->logicals, g->logicals.size() * sizeof(uint64_t)));
+        SAGMS_HIP(hipMemcpy(t->logicals, g->logicals.data(), g->logicals.size() * sizeof(uint64_t),
+                            hipMemcpyHostToDevice));
+    }
+    const LayeredHost& lh = g->layered;
+    if (lh.status == SAGMS_OK) {
+        LayeredPlan& lp = t->layered;
+        lp.dc = lh.dc;
+        lp.group = lh.group;
+        lp.passes = lh.passes;
+        lp.npad = lh.npad;
+        lp.group_words = lh.group_words;
+        lp.table_words = lh.table_words;
+        lp.regs = lh.regs;
+        SAGMS_HIP(hipMalloc(&lp.pass_check, lh.pass_check.size() * sizeof(int32_t)));
+        SAGMS_HIP(hipMemcpy(lp.pass_check, lh.pass_check.data(), lh.pass_check.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice));
+        SAGMS_HIP(hipMalloc(&lp.check_vars, lh.check_vars.size() * sizeof(uint32_t)));
+        SAGMS_HIP(hipMemcpy(lp.check_vars, lh.check_vars.data(), lh.check_vars.size() * sizeof(uint32_t),
+                            hipMemcpyHostToDevice));
+    }
+    return SAGMS_OK;
+}
+
+static void free_tables(DeviceTables* t) {
+    (void)hipFree(t->cols);
+    (void)hipFree(t->rows);
+    (void)hipFree(t->cn_addr);
+    (void)hipFree(t->vn_addr);
+    (void)hipFree(t->logicals);
+    (void)hipFree(t->layered.pass_check);
+    (void)hipFree(t->layered.check_vars);
+    *t = DeviceTables{};
+}
+
+int upload_tables(Graph* g, DeviceTables** out) {
     int dev = 0;
     SAGMS_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= kMaxDevices) return fail(SAGMS_EUNSUPPORTED, "device index %d too large", dev);
     std::lock_guard<std::mutex> lock(g->mu);
     DeviceTables* t = &g->dev[dev];
     if (!t->ready) {
-        size_t ncols = (size_t)g->m * std::max(g->dc_max, 1);
-        std::vector<int32_t> cols(ncols, -1);
-        for (int c = 0; c < g->m; ++c)
-            for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p)
-                cols[(size_t)c * std::max(g->dc_max, 1) + p] = g->cols[g->row_ptr[c] + p];
-        SAGMS_HIP(hipMalloc(&t->cols, std::max<size_t>(ncols, 1) * sizeof(int32_t)));
-        SAGMS_HIP(hipMemcpy(t->cols, cols.data(), ncols * sizeof(int32_t), hipMemcpyHostToDevice));
-        SAGMS_HIP(hipMalloc(&t->rows, g->rows_bits.size() * sizeof(uint64_t)));
-        SAGMS_HIP(hipMemcpy(t->rows, g->rows_bits.data(), g->rows_bits.size() * sizeof(uint64_t),
-                            hipMemcpyHostToDevice));
-        if (g->shape_ok) {
-            SAGMS_HIP(hipMalloc(&t->cn_addr, g->cn_addr_host.size() * sizeof(uint32_t)));
-            SAGMS_HIP(hipMemcpy(t->cn_addr, g->cn_addr_host.data(), g->cn_addr_host.size() * sizeof(uint32_t),
-                                hipMemcpyHostToDevice));
-            SAGMS_HIP(hipMalloc(&t->vn_addr, g->vn_addr_host.size() * sizeof(uint32_t)));
-            SAGMS_HIP(hipMemcpy(t->vn_addr, g->vn_addr_host.data(), g->vn_addr_host.size() * sizeof(uint32_t),
-                                hipMemcpyHostToDevice));
-        }
-        if (g->k > 0) {
-            SAGMS_HIP(hipMalloc(&t->logicals, g->logicals.size() * sizeof(uint64_t)));
-            SAGMS_HIP(hipMemcpy(t->logicals, g->logicals.data(), g->logicals.size() * sizeof(uint64_t),
-                                hipMemcpyHostToDevice));
+        const int rc = upload_locked(g, t);
+        if (rc) {
+            free_tables(t);
+            return rc;
         }
         t->ready = true;
     }
-    (void)stream;
     *out = t;
     return SAGMS_OK;
 }
 
-// Gain law of eq. (alphaeff), tabulated over the residual-syndrome weight w
-// in IEEE double and rounded to float (pairs: satisfied, unsatisfied check).
-static std::vector<float> make_gains(const GainKey& key, int m, int entries) {
-    std::vector<float> t(2 * (size_t)entries, 1.0f);
-    for (int w = 0; w <= m && w < entries; ++w) {
-        double gs = 1.0, gu = 1.0;
-        if (key.kind == SAGMS_SMS) {
-            gs = gu = key.a;
-        } else if (key.kind == SAGMS_SAGMS) {
-            double gamma = (double)w / (double)m;
-            double gl = key.amax - (key.amax - key.amin) * gamma;
-            gs = gl;
-            gu = gl * key.eta;
-        }
-        t[2 * (size_t)w] = (float)gs;
-        t[2 * (size_t)w + 1] = (float)gu;
-    }
-    return t;
-}
-
-int gain_table(Graph* g, DeviceTables* t, const GainKey& key, const float** out, hipStream_t stream) {
+int device_tables(Graph* g, DeviceTables** out) {
+    int dev = 0;
+    SAGMS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SAGMS_EUNSUPPORTED, "device index %d too large", dev);
     std::lock_guard<std::mutex> lock(g->mu);
-    auto it = t->gains.find(key);
-    if (it != t->gains.end()) {
-        *out = it->second;
-        return SAGMS_OK;
-    }
-    int entries = g->layout.cw + 1;
-    std::vector<float>& host = t->gains_host[key];
-    host = make_gains(key, g->m, entries);
-    float* d = nullptr;
-    SAGMS_HIP(hipMalloc(&d, host.size() * sizeof(float)));
-    SAGMS_HIP(hipMemcpyAsync(d, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, stream));
-    t->gains[key] = d;
-    *out = d;
+    DeviceTables* t = &g->dev[dev];
+    if (!t->ready)
+        return fail(SAGMS_EINVAL, "the graph has no tables on device %d: call sagms_graph_upload with it current", dev);
+    *out = t;
     return SAGMS_OK;
 }
 
@@ -436,21 +461,18 @@ int sagms_destroy_graph(sagms_graph gh) {
         DeviceTables& t = g->dev[d];
         if (!t.ready) continue;
         if (have_dev) (void)hipSetDevice(d);
-        (void)hipFree(t.cols);
-        (void)hipFree(t.rows);
-        (void)hipFree(t.cn_addr);
-        (void)hipFree(t.vn_addr);
-        (void)hipFree(t.logicals);
-        for (auto& kv : t.gains) (void)hipFree(kv.second);
-        if (t.layered) {
-            (void)hipFree(t.layered->pass_check);
-            (void)hipFree(t.layered->check_vars);
-            delete t.layered;
-        }
+        free_tables(&t);
     }
     if (have_dev) (void)hipSetDevice(cur);
     delete g;
     return SAGMS_OK;
+}
+
+int sagms_graph_upload(sagms_graph gh) {
+    Graph* g = reinterpret_cast<Graph*>(gh);
+    if (!g) return fail(SAGMS_EINVAL, "null graph");
+    DeviceTables* t = nullptr;
+    return upload_tables(g, &t);
 }
 
 double sagms_alpha_star(double l0, int32_t dc) {

@@ -70,12 +70,14 @@ struct DecodeLayout {
     int cw, zero, post0, padpost, gain0, words;
 };
 
-struct GainKey {
-    int kind;
+// Gain law of a decoder configuration (eq. (alphaeff)): kind MS / BP (gain
+// 1), SMS (alpha), SAGMS (alpha_min, alpha_max, eta).  The kernels evaluate
+// it per residual weight w in IEEE double, operation by operation, and round
+// to float (gain_pair, decode_core.h), so no table is allocated per call.
+struct GainLaw {
+    int32_t kind;
+    int32_t pad;
     double a, amin, amax, eta;
-    bool operator<(const GainKey& o) const {
-        return std::tie(kind, a, amin, amax, eta) < std::tie(o.kind, o.a, o.amin, o.amax, o.eta);
-    }
 };
 
 // Layered schedule (layered.hip, layers.cpp): the checks in layers of checks
@@ -90,23 +92,36 @@ struct GainKey {
 // registers (layered.hip); longer ones keep them in LDS.
 constexpr int kLayeredRegPasses = 16;
 
-struct LayeredPlan {
+// Host part of the layered plan, computed when the graph is built; status
+// is SAGMS_OK when the layered schedule can run the graph, else the code
+// returned by a layered decode, with `why` as its message.
+struct LayeredHost {
+    int status = SAGMS_EUNSUPPORTED;
+    std::string why;
     int dc = 0, group = 0, passes = 0, npad = 0, group_words = 0, table_words = 0;
     bool regs = false;  // check outputs in registers (passes <= kLayeredRegPasses)
-    int32_t* pass_check = nullptr;   // device [passes][group], -1 = idle lane
-    uint32_t* check_vars = nullptr;  // device [m][dc / 2] variable pairs as 16-bit byte offsets 4 j
+    std::vector<int32_t> pass_check;   // [passes][group], -1 = idle lane
+    std::vector<uint32_t> check_vars;  // [m][dc / 2] variable pairs as 16-bit byte offsets 4 j
 };
 
+struct LayeredPlan {
+    int dc = 0, group = 0, passes = 0, npad = 0, group_words = 0, table_words = 0;
+    bool regs = false;
+    int32_t* pass_check = nullptr;   // device copy of LayeredHost::pass_check
+    uint32_t* check_vars = nullptr;  // device copy of LayeredHost::check_vars
+};
+
+// Device copies of a graph's tables on one HIP device, created by
+// upload_tables (graph build, sagms_graph_upload, batch and server set-up)
+// and never on a decode, sampling or judge call.
 struct DeviceTables {
     bool ready = false;
-    LayeredPlan* layered = nullptr;  // created on the first layered decode
+    LayeredPlan layered;           // valid when the graph's LayeredHost status is SAGMS_OK
     uint32_t* cn_addr = nullptr;   // [cpl * dc][64] LDS word index of the posterior read at (check, pos)
     uint32_t* vn_addr = nullptr;   // [vpl * dv][64] LDS word index of the c2v slot read at (var, rank)
     int32_t* cols = nullptr;       // [m][dc_max] column of (check, pos), -1 padded (sampler)
     uint64_t* rows = nullptr;      // [m][words_n] packed rows of H (sampler)
     uint64_t* logicals = nullptr;  // [k][words_n]
-    std::map<GainKey, float*> gains;
-    std::map<GainKey, std::vector<float>> gains_host;  // kept alive for async uploads
 };
 
 struct Graph {
@@ -127,6 +142,7 @@ struct Graph {
     DecodeShape shape{};
     DecodeLayout layout{};
     std::vector<uint32_t> cn_addr_host, vn_addr_host;
+    LayeredHost layered;
     std::mutex mu;
     DeviceTables dev[kMaxDevices];
 };
@@ -134,10 +150,14 @@ struct Graph {
 // GF(2) helpers (graph.cpp)
 int gf2_rank(std::vector<uint64_t> rows, int nrows, int wn);
 
-// Returns the device tables of g on the current device, creating them once.
-int device_tables(Graph* g, DeviceTables** out, hipStream_t stream);
-// Device gain table for a decoder configuration (created once per device).
-int gain_table(Graph* g, DeviceTables* t, const GainKey& key, const float** out, hipStream_t stream);
+// Creates the device tables of g on the current device (once; later calls
+// return them).  Allocates and copies synchronously: set-up calls only.
+int upload_tables(Graph* g, DeviceTables** out);
+// The device tables of g on the current device; SAGMS_EINVAL if they were
+// never uploaded there.  Allocates nothing.
+int device_tables(Graph* g, DeviceTables** out);
+// Layered plan of g computed on the host (layers.cpp), stored in g->layered.
+void plan_layers(Graph* g);
 
 // Shape selection for the decode kernels.
 bool pick_shape(int m, int n, int dc, int dv, DecodeShape* out);
@@ -147,7 +167,7 @@ DecodeLayout make_layout(const DecodeShape& s);
 struct DecodeArgs {
     const uint64_t* synd;
     const float* llr0;
-    const float* gains;  // [cw + 1] pairs (gain of a satisfied, of an unsatisfied check) by residual weight
+    GainLaw gains;       // per-round gains by residual weight (gain_pair)
     const uint32_t* cn_addr;
     const uint32_t* vn_addr;
     uint64_t* ehat;
@@ -159,18 +179,16 @@ struct DecodeArgs {
     DecodeLayout L;
 };
 int launch_decode(const DecodeShape& s, bool bp, int msg_precision, const DecodeArgs& a, hipStream_t st);
-// The layered plan of g on the current device (created once; layers.cpp).
-int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t st);
 int launch_layered(const LayeredPlan& plan, const DecodeArgs& a, hipStream_t st);
 
 constexpr int kDecodeFramesPerWave = 16;  // frames per wave before the taper
 constexpr int kMixedTileFrames = 8;       // default tile of a mixed-code batch
 // Decoder configuration checks (api.cpp); SAGMS_OK or a status.
 int check_cfg(const sagms_decoder_cfg* c);
-// Device gain table of a configuration on the current device.
-int cfg_gains(Graph* g, DeviceTables* t, const sagms_decoder_cfg* cfg, const float** out, hipStream_t st);
+// Gain law of a configuration (checked by check_cfg).
+GainLaw gain_law(const sagms_decoder_cfg* cfg);
 // Kernel arguments of one decode call (frames_per_wave 0 = default).
-DecodeArgs decode_args(const Graph* g, const DeviceTables* t, const float* gains, const uint64_t* synd,
+DecodeArgs decode_args(const Graph* g, const DeviceTables* t, const GainLaw& gains, const uint64_t* synd,
                        const float* llr0, int64_t nframes, uint64_t* ehat, int32_t* iters, uint8_t* converged,
                        float* posterior, int lmax, int frames_per_wave);
 

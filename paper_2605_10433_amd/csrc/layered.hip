@@ -88,7 +88,7 @@ layered_kernel(LayeredArgs la) {
 
     for (int t = lane; t < la.P * G; t += 64) t_pass[t] = (uint32_t)la.pass_check[t];
     for (int t = lane; t < m * (DC / 2); t += 64) t_vars[t] = la.check_vars[t];
-    for (int t = lane; t < 2 * (m + 1); t += 64) t_gain[t] = a.gains[t];
+    write_gains(a.gains, m, m + 1, t_gain, lane);
     for (int t = lane; t < n; t += 64) t_l0[t] = a.llr0[t] + 0.0f;  // -0 reads as +0
     __syncthreads();
     // H [L0 < 0] (mod 2): a frame's first residual is its syndrome xor this
@@ -117,8 +117,11 @@ layered_kernel(LayeredArgs la) {
     int64_t f = -1;                              // frame being decoded
     int64_t res = f_begin + grp < f_end ? f_begin + grp : -1;  // reserved next frame
     int64_t next = f_begin + F;                  // wave-uniform: next unclaimed frame
-    uint64_t res_word = 0;                       // lanes q < wm: word q of res's syndrome
-    if (res >= 0 && q < wm) res_word = a.synd[res * wm + q];
+    // lanes q < wm: word q of res's syndrome, its bits at or above m cleared
+    // (the caller's padding bits are not syndrome bits)
+    const uint64_t keep = q == wm - 1 && (m & 63) ? (1ull << (m & 63)) - 1 : ~0ull;
+    uint64_t res_word = 0;
+    if (res >= 0 && q < wm) res_word = a.synd[res * wm + q] & keep;
     int it = 0, w = 0;
     bool active = false;
     // PMAX > 0: outputs of the lane's check in pass p (S1, S1 ^ S2, mask)
@@ -222,7 +225,7 @@ layered_kernel(LayeredArgs la) {
                 const int rank = __popcll(leaders & ((1ull << (grp * G)) - 1));
                 const int64_t claim = next + rank;
                 res = claim < f_end ? claim : -1;
-                if (res >= 0 && q < wm) res_word = a.synd[res * wm + q];
+                if (res >= 0 && q < wm) res_word = a.synd[res * wm + q] & keep;
             }
             next += __popcll(leaders);
             int w0 = 0;

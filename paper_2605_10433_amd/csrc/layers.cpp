@@ -1,7 +1,8 @@
 // Host side of the layered schedule: the layers of a graph (first fit in
 // ascending check index: check i joins the first layer none of whose checks
 // shares a variable with it, else opens a new one), their passes of at most
-// `group` checks, and the device tables of layered.hip.
+// `group` checks, and the host copies of the tables of layered.hip (uploaded
+// with the graph's other device tables).
 #include <algorithm>
 
 #include "internal.h"
@@ -16,21 +17,22 @@ int round4(int x) { return (x + 3) & ~3; }
 
 }  // namespace
 
-int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t st) {
-    std::lock_guard<std::mutex> lock(g->mu);
-    if (t->layered) {
-        *out = t->layered;
-        return SAGMS_OK;
-    }
+static int refuse(LayeredHost* lh, const char* why) {
+    lh->status = SAGMS_EUNSUPPORTED;
+    lh->why = why;
+    return lh->status;
+}
+
+static int plan(const Graph* g, LayeredHost* lh) {
     const int m = g->m, n = g->n;
     const int dc = g->row_ptr[1] - g->row_ptr[0];
     for (int c = 0; c < m; ++c)
         if (g->row_ptr[c + 1] - g->row_ptr[c] != dc)
-            return fail(SAGMS_EUNSUPPORTED, "layered schedule: needs every check of the same degree");
-    if (dc != 6 && dc != 8 && dc != 10)
-        return fail(SAGMS_EUNSUPPORTED, "layered schedule: check degree %d not compiled (6, 8 or 10)", dc);
+            return refuse(lh, "layered schedule: needs every check of the same degree");
+    if (dc != 6 && dc != 8 && dc != 10) return refuse(lh, "layered schedule: check degree not compiled (6, 8 or 10)");
+    if (!g->shape_ok) return refuse(lh, "layered schedule: no decode kernel fits the graph");
     // variables are held as 16-bit byte offsets (4 j)
-    if (n > 0x3FFF) return fail(SAGMS_EUNSUPPORTED, "layered schedule: n must be < 16384");
+    if (n > 0x3FFF) return refuse(lh, "layered schedule: n must be < 16384");
 
     // first-fit layers
     std::vector<std::vector<int>> layers;
@@ -57,60 +59,44 @@ int layered_plan(Graph* g, DeviceTables* t, const LayeredPlan** out, hipStream_t
     int group = 8;
     while (group < 64 && (size_t)group < need) group *= 2;
     if ((size_t)g->wm > (size_t)group || (size_t)g->wn > (size_t)group)
-        return fail(SAGMS_EUNSUPPORTED, "layered schedule: code too long");
+        return refuse(lh, "layered schedule: code too long");
 
-    std::vector<int32_t> pass_check;
+    lh->pass_check.clear();
     int passes = 0;
     for (const auto& l : layers)
         for (size_t b = 0; b < l.size(); b += group) {
-            for (int q = 0; q < group; ++q) pass_check.push_back(b + q < l.size() ? l[b + q] : -1);
+            for (int q = 0; q < group; ++q) lh->pass_check.push_back(b + q < l.size() ? l[b + q] : -1);
             ++passes;
         }
-    std::vector<uint32_t> check_vars((size_t)m * (dc / 2));
+    lh->check_vars.assign((size_t)m * (dc / 2), 0u);
     for (int c = 0; c < m; ++c)
         for (int k = 0; k < dc / 2; ++k)
-            check_vars[(size_t)c * (dc / 2) + k] = (uint32_t)(4 * g->cols[g->row_ptr[c] + 2 * k]) |
-                                                   ((uint32_t)(4 * g->cols[g->row_ptr[c] + 2 * k + 1]) << 16);
-
-    auto* plan = new LayeredPlan();
-    plan->dc = dc;
-    plan->group = group;
-    plan->passes = passes;
-    plan->npad = round4(n);
-    plan->regs = passes <= kLayeredRegPasses;
+            lh->check_vars[(size_t)c * (dc / 2) + k] = (uint32_t)(4 * g->cols[g->row_ptr[c] + 2 * k]) |
+                                                       ((uint32_t)(4 * g->cols[g->row_ptr[c] + 2 * k + 1]) << 16);
+    lh->dc = dc;
+    lh->group = group;
+    lh->passes = passes;
+    lh->npad = round4(n);
+    lh->regs = passes <= kLayeredRegPasses;
     // every group of a wavefront updates the same check in the same pass, so
     // its lanes read the same offsets of their own slices.  With the check
     // outputs in LDS, slices 4 words apart modulo the LDS banks keep those
     // reads (and the 4-word reads of a check's compressed outputs) on
     // different banks; with them in registers, the 32 / G groups of a
     // half-wavefront (32 banks) sit G words apart modulo 32.
-    if (plan->regs)
-        plan->group_words = (plan->npad + 4 * g->wm + 31) / 32 * 32 + (group < 32 ? group : 0);
+    if (lh->regs)
+        lh->group_words = (lh->npad + 4 * g->wm + 31) / 32 * 32 + (group < 32 ? group : 0);
     else
-        plan->group_words = (plan->npad + 4 * m + 4 * g->wm + 63) / 64 * 64 + 4;
-    plan->table_words = round4(passes * group + m * (dc / 2) + 2 * (m + 1) + n + 2 * g->wm);
+        lh->group_words = (lh->npad + 4 * m + 4 * g->wm + 63) / 64 * 64 + 4;
+    lh->table_words = round4(passes * group + m * (dc / 2) + 2 * (m + 1) + n + 2 * g->wm);
     const int frames = 64 / group;
-    if ((size_t)(plan->table_words + frames * plan->group_words) * 4 > (size_t)kLayeredMaxLds) {
-        delete plan;
-        return fail(SAGMS_EUNSUPPORTED, "layered schedule: code too large for one wavefront's LDS");
-    }
-    hipError_t e = hipMalloc(&plan->pass_check, pass_check.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(&plan->check_vars, check_vars.size() * sizeof(uint32_t));
-    if (e == hipSuccess)
-        e = hipMemcpy(plan->pass_check, pass_check.data(), pass_check.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(plan->check_vars, check_vars.data(), check_vars.size() * sizeof(uint32_t),
-                      hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        if (plan->pass_check) (void)hipFree(plan->pass_check);
-        if (plan->check_vars) (void)hipFree(plan->check_vars);
-        delete plan;
-        return hip_fail(e, "layered tables");
-    }
-    (void)st;
-    t->layered = plan;
-    *out = plan;
+    if ((size_t)(lh->table_words + frames * lh->group_words) * 4 > (size_t)kLayeredMaxLds)
+        return refuse(lh, "layered schedule: code too large for one wavefront's LDS");
+    lh->status = SAGMS_OK;
+    lh->why.clear();
     return SAGMS_OK;
 }
+
+void plan_layers(Graph* g) { (void)plan(g, &g->layered); }
 
 }  // namespace sagms

@@ -28,7 +28,6 @@ constexpr int kMaxServerStreams = 8;
 struct Code {
     Graph* g = nullptr;
     DeviceTables* t = nullptr;
-    const float* gains = nullptr;
     float* llr0 = nullptr;  // device copy
     int tier = 0, shape = 0;
 };
@@ -173,7 +172,7 @@ int launch(Server* s, Slot& x, int tier, double t) {
     for (const Seg& g : x.segs) {
         const Code& c = s->codes[g.code];
         MixedSegment m{};
-        m.a = decode_args(c.g, c.t, c.gains, x.d_in + g.in_word, c.llr0, g.frames,
+        m.a = decode_args(c.g, c.t, gain_law(&s->cfg), x.d_in + g.in_word, c.llr0, g.frames,
                           reinterpret_cast<uint64_t*>(x.d_out) + g.ehat_word,
                           reinterpret_cast<int32_t*>(x.d_out + g.iters_off), x.d_out + g.conv_off, nullptr,
                           s->cfg.lmax, 0);
@@ -308,8 +307,7 @@ int sagms_server_create(const sagms_graph* graphs, const float* const* llr0_host
         k.g = reinterpret_cast<Graph*>(graphs[c]);
         k.shape = shape_index(k.g->shape);
         k.tier = mixed_tier_of_shape(k.shape);
-        rc = device_tables(k.g, &k.t, nullptr);
-        if (!rc) rc = cfg_gains(k.g, k.t, cfg, &k.gains, nullptr);
+        rc = upload_tables(k.g, &k.t);
         if (!rc) {
             e = hipMalloc(&k.llr0, sizeof(float) * k.g->n);
             if (e == hipSuccess) e = hipMemcpy(k.llr0, llr0_host[c], sizeof(float) * k.g->n, hipMemcpyHostToDevice);
