@@ -347,6 +347,27 @@ int sagms_batch_tune(sagms_batch b, void* stream, int32_t reps, sagms_tune_resul
 
 int sagms_batch_destroy(sagms_batch b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one decode
+ * of nseg (1..16) segments, as sagms_batch_create + sagms_batch_run with
+ * `plan` (NULL = the initial plan of a batch: SINGLE, tile_frames 8,
+ * waves_per_block 4), without a batch object.  Same checks and status codes
+ * as sagms_batch_create and sagms_batch_set_plan; every frame's outputs equal
+ * those of sagms_decode on that segment alone, bit for bit.
+ *   Allocates nothing: no hipMalloc or hipFree, no host-to-device copy.  The
+ *   persistent launches' work-queue counters live in a library-owned static
+ *   device array of 16 KiB per device (4 register classes x 16 queues),
+ *   held until the process ends and reset by a kernel at every launch.  Its
+ *   address is taken when a graph is first uploaded to the device, so the
+ *   graphs must have their tables on the current device (SAGMS_EINVAL
+ *   otherwise).  More segments than 16 are refused (SAGMS_EINVAL).
+ *   The array is shared by every call on a device: calls that overlap in
+ *   time on one device (on different streams, or from several threads) race
+ *   on it and must be ordered by the caller, e.g. on one stream.  The
+ *   PER_CODE plan uses no queue counters. */
+int sagms_decode_segments(const sagms_segment* segs, int32_t nseg, const sagms_decoder_cfg* cfg,
+                          const sagms_plan* plan, void* stream);
+
 /* ---- serving ----------------------------------------------------------
  * Continuous batching of decode requests (Algorithm 1 on each request's
  * frames, one decoder configuration, several codes).  Requests wait in one

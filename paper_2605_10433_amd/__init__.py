@@ -107,6 +107,7 @@ def lib():
             "sagms_batch_instantiate": [vp],
             "sagms_batch_tune": [vp, vp, i32, vp, i32, vp, vp],
             "sagms_batch_destroy": [vp],
+            "sagms_decode_segments": [vp, i32, vp, vp, vp],
             "sagms_server_create": [vp, vp, i32, vp, vp, vp],
             "sagms_server_submit": [vp, vp, vp],
             "sagms_server_progress": [vp, vp, i32, vp],
@@ -318,6 +319,33 @@ def frame_buffers(g: Graph, nframes: int, device="cuda", with_ez=True):
     )
 
 
+def _segment_array(segments):
+    """The sagms_segment array of a list of segment dicts (see Batch)."""
+    import torch
+    n = len(segments)
+    arr = (Segment * max(n, 1))()
+    for i, sg in enumerate(segments):
+        g = sg["graph"]
+        nf = int(sg["synd"].shape[0])
+        arr[i].graph = g._h.value if g is not None else None
+        arr[i].synd = _dev_ptr(sg["synd"], torch.int64, (nf, g.words_m), "synd")
+        arr[i].llr0 = _dev_ptr(sg["llr0"], torch.float32, (g.n,), "llr0")
+        arr[i].nframes = nf
+        arr[i].ehat = _dev_ptr(sg["ehat"], torch.int64, (nf, g.words_n), "ehat")
+        arr[i].iters = _dev_ptr(sg["iters"], torch.int32, (nf,), "iters")
+        arr[i].converged = _dev_ptr(sg["converged"], torch.uint8, (nf,), "converged")
+        arr[i].posterior = _dev_ptr(sg.get("posterior"), torch.float32, (nf, g.n), "posterior")
+    return arr, n
+
+
+def decode_segments(segments, cfg: DecoderConfig, plan_: Plan = None, stream=None):
+    """One mixed-code decode without a batch object or any allocation
+    (``sagms_decode_segments``); segments as for Batch."""
+    arr, n = _segment_array(segments)
+    _check(lib().sagms_decode_segments(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.byref(cfg),
+                                       ctypes.byref(plan_) if plan_ is not None else None, _stream(stream)))
+
+
 class Batch:
     """A mixed-code batch (``sagms_batch_*``).
 
@@ -328,22 +356,8 @@ class Batch:
     """
 
     def __init__(self, segments, cfg: DecoderConfig):
-        import torch
-        n = len(segments)
-        arr = (Segment * max(n, 1))()
-        self._keep = []
-        for i, sg in enumerate(segments):
-            g = sg["graph"]
-            nf = int(sg["synd"].shape[0])
-            arr[i].graph = g._h.value if g is not None else None
-            arr[i].synd = _dev_ptr(sg["synd"], torch.int64, (nf, g.words_m), "synd")
-            arr[i].llr0 = _dev_ptr(sg["llr0"], torch.float32, (g.n,), "llr0")
-            arr[i].nframes = nf
-            arr[i].ehat = _dev_ptr(sg["ehat"], torch.int64, (nf, g.words_n), "ehat")
-            arr[i].iters = _dev_ptr(sg["iters"], torch.int32, (nf,), "iters")
-            arr[i].converged = _dev_ptr(sg["converged"], torch.uint8, (nf,), "converged")
-            arr[i].posterior = _dev_ptr(sg.get("posterior"), torch.float32, (nf, g.n), "posterior")
-            self._keep.append(sg)
+        arr, n = _segment_array(segments)
+        self._keep = list(segments)
         self._cfg = cfg
         h = ctypes.c_void_p()
         _check(lib().sagms_batch_create(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.byref(cfg), ctypes.byref(h)))

@@ -2,6 +2,7 @@
 // plan autotuner.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 
 #include "internal.h"
@@ -24,16 +25,24 @@ int mixed_waves_of(int tier, int requested) {
     return w;
 }
 
+OccupancyCache::OccupancyCache() {
+    for (auto& a : blocks)
+        for (auto& b : a)
+            for (auto& c : b)
+                for (int& d : c) d = -1;
+}
+
 int OccupancyCache::get(int tier, int budget, int mt, int wpb, int* out) {
-    const auto key = std::make_tuple(tier, budget, mt, wpb);
-    auto it = blocks.find(key);
-    if (it == blocks.end()) {
+    if (tier < 0 || tier >= kNumMixedTiers || budget < 0 || budget > 1 || mt < 0 || mt > 2 || wpb < 1 || wpb > 4)
+        return fail(SAGMS_EINVAL, "occupancy key out of range (internal)");
+    int& slot = blocks[tier][budget][mt][wpb];
+    if (slot < 0) {
         int n = 0;
         int rc = mixed_max_blocks(tier, budget, mt, wpb, &n);
         if (rc) return rc;
-        it = blocks.emplace(key, n).first;
+        slot = n;
     }
-    *out = it->second;
+    *out = slot;
     return SAGMS_OK;
 }
 
@@ -68,6 +77,100 @@ int launch_segments(const MixedSegment* segs, int nseg, int tier, const MixedLau
     return launch_mixed(tier, budget, mt, m, (int)blocks, wpb, st);
 }
 
+int prepare_segments(const sagms_segment* segs, int nseg, const sagms_decoder_cfg* cfg, bool upload,
+                     SegmentSet* out) {
+    if (!segs) return fail(SAGMS_EINVAL, "segs is null");
+    if (nseg < 1 || nseg > kMaxSegments) return fail(SAGMS_EINVAL, "nseg must lie in [1, %d]", kMaxSegments);
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (cfg->kind == SAGMS_BP) return fail(SAGMS_EUNSUPPORTED, "batches run MS, SMS and SAGMS only");
+    if (cfg->schedule != SAGMS_FLOODING) return fail(SAGMS_EUNSUPPORTED, "batches run the flooding schedule only");
+    for (int s = 0; s < nseg; ++s) {
+        const sagms_segment& x = segs[s];
+        Graph* g = reinterpret_cast<Graph*>(x.graph);
+        if (!g) return fail(SAGMS_EINVAL, "segment %d: null graph", s);
+        if (!g->shape_ok) return fail(SAGMS_EUNSUPPORTED, "segment %d: no decode kernel fits the code", s);
+        if (shape_index(g->shape) < 0) return fail(SAGMS_EUNSUPPORTED, "segment %d: shape not compiled", s);
+        if (x.nframes < 0) return fail(SAGMS_EINVAL, "segment %d: nframes must be >= 0", s);
+        if (x.nframes > 0 && (!x.synd || !x.llr0 || !x.ehat || !x.iters || !x.converged))
+            return fail(SAGMS_EINVAL, "segment %d: null buffer", s);
+    }
+    // launch order: largest register tier first, then the most lane slots per
+    // round (the most expensive frames first), then the caller's order
+    // (insertion sort on a fixed array: stable, no allocation)
+    int order[kMaxSegments];
+    auto cost = [&](int s) {
+        const DecodeShape& sh = reinterpret_cast<Graph*>(segs[s].graph)->shape;
+        return sh.cpl * sh.dc + sh.vpl * sh.dv;
+    };
+    auto tier = [&](int s) { return mixed_tier_of_shape(shape_index(reinterpret_cast<Graph*>(segs[s].graph)->shape)); };
+    auto before = [&](int x, int y) { return tier(x) != tier(y) ? tier(x) > tier(y) : cost(x) > cost(y); };
+    for (int s = 0; s < nseg; ++s) {
+        int i = s;
+        while (i > 0 && before(s, order[i - 1])) {
+            order[i] = order[i - 1];
+            --i;
+        }
+        order[i] = s;
+    }
+    out->nseg = nseg;
+    for (int i = 0; i < nseg; ++i) {
+        const int s = order[i];
+        const sagms_segment& x = segs[s];
+        Graph* g = reinterpret_cast<Graph*>(x.graph);
+        DeviceTables* t = nullptr;
+        rc = upload ? upload_tables(g, &t) : device_tables(g, &t);
+        if (rc) return rc;
+        MixedSegment ms{};
+        ms.a = decode_args(g, t, gain_law(cfg), x.synd, x.llr0, x.nframes, x.ehat, x.iters, x.converged, x.posterior,
+                           cfg->lmax, 0);
+        ms.shape = shape_index(g->shape);
+        out->segs[i] = ms;
+        out->tier[i] = tier(s);
+        out->shape[i] = g->shape;
+    }
+    return SAGMS_OK;
+}
+
+int check_plan(const sagms_plan* p) {
+    if (!p) return fail(SAGMS_EINVAL, "plan is null");
+    if (p->kind < SAGMS_PLAN_SINGLE || p->kind > SAGMS_PLAN_PER_CODE) return fail(SAGMS_EINVAL, "unknown plan kind %d", p->kind);
+    if (p->tile_frames < 1 || p->tile_frames > 1024) return fail(SAGMS_EINVAL, "tile_frames must lie in [1, 1024]");
+    if (p->reserved != 0) return fail(SAGMS_EINVAL, "reserved field must be 0");
+    if (p->kind == SAGMS_PLAN_PER_CODE) return SAGMS_OK;
+    if (p->waves_per_block != 1 && p->waves_per_block != 2 && p->waves_per_block != 4)
+        return fail(SAGMS_EINVAL, "waves_per_block must be 1, 2 or 4");
+    if (p->blocks_per_cu < 0 || p->blocks_per_cu > 64) return fail(SAGMS_EINVAL, "blocks_per_cu must lie in [0, 64]");
+    if (p->reg_budget != 0 && p->reg_budget != 1) return fail(SAGMS_EINVAL, "reg_budget must be 0 or 1");
+    return SAGMS_OK;
+}
+
+int enqueue_segments(const SegmentSet& set, const sagms_plan& p, int mt, int num_cu, uint32_t* queues,
+                     OccupancyCache* occ, hipStream_t st) {
+    if (p.kind == SAGMS_PLAN_PER_CODE) {
+        for (int s = 0; s < set.nseg; ++s) {
+            if (set.segs[s].a.nframes == 0) continue;
+            DecodeArgs a = set.segs[s].a;
+            a.frames_per_wave = p.tile_frames;
+            int rc = launch_decode(set.shape[s], false, mt, a, st);
+            if (rc) return rc;
+        }
+        return SAGMS_OK;
+    }
+    const MixedLaunch L{p.tile_frames, p.waves_per_block, p.blocks_per_cu, p.reg_budget};
+    // SINGLE: one launch with the largest tier's kernel; TIERED: one per tier
+    for (int s0 = 0; s0 < set.nseg;) {
+        int s1 = s0;
+        while (s1 < set.nseg && (p.kind == SAGMS_PLAN_SINGLE || set.tier[s1] == set.tier[s0])) ++s1;
+        const int tier = set.tier[s0];
+        int rc = launch_segments(set.segs + s0, s1 - s0, tier, L, num_cu, mt,
+                                 queues + (size_t)tier * kMaxQueues * kQueueStride, occ, st);
+        if (rc) return rc;
+        s0 = s1;
+    }
+    return SAGMS_OK;
+}
+
 }  // namespace sagms
 
 using namespace sagms;
@@ -78,12 +181,8 @@ struct Batch {
     int device = 0;
     sagms_decoder_cfg cfg{};
     int mt = SAGMS_MSG_FP32;
-    int nseg = 0;
     int num_cu = 0;
-    // segments in launch order: register tier descending, then cost per frame
-    std::vector<MixedSegment> segs;
-    std::vector<int> tier;     // per segment
-    std::vector<DecodeShape> shape;
+    SegmentSet set;                // segments in launch order
     uint32_t* d_queues = nullptr;  // kNumMixedTiers blocks of kMaxQueues counters
     sagms_plan plan{};
     hipGraph_t graph = nullptr;
@@ -98,54 +197,14 @@ void drop_graph(Batch* b) {
     b->graph = nullptr;
 }
 
-int check_plan(const Batch*, const sagms_plan* p) {
-    if (!p) return fail(SAGMS_EINVAL, "plan is null");
-    if (p->kind < SAGMS_PLAN_SINGLE || p->kind > SAGMS_PLAN_PER_CODE) return fail(SAGMS_EINVAL, "unknown plan kind %d", p->kind);
-    if (p->tile_frames < 1 || p->tile_frames > 1024) return fail(SAGMS_EINVAL, "tile_frames must lie in [1, 1024]");
-    if (p->reserved != 0) return fail(SAGMS_EINVAL, "reserved field must be 0");
-    if (p->kind == SAGMS_PLAN_PER_CODE) return SAGMS_OK;
-    if (p->waves_per_block != 1 && p->waves_per_block != 2 && p->waves_per_block != 4)
-        return fail(SAGMS_EINVAL, "waves_per_block must be 1, 2 or 4");
-    if (p->blocks_per_cu < 0 || p->blocks_per_cu > 64) return fail(SAGMS_EINVAL, "blocks_per_cu must lie in [0, 64]");
-    if (p->reg_budget != 0 && p->reg_budget != 1) return fail(SAGMS_EINVAL, "reg_budget must be 0 or 1");
-    return SAGMS_OK;
-}
-
 int blocks_per_cu(Batch* b, int tier, int* out) {
     const int budget = mixed_budget_of(tier, b->plan.reg_budget);
     const int wpb = mixed_waves_of(tier, b->plan.waves_per_block);
     return b->occupancy.get(tier, budget, b->mt, wpb, out);
 }
 
-// One persistent launch over segments [s0, s1) with the kernel of `tier`.
-int launch_group(Batch* b, int s0, int s1, int tier, hipStream_t st) {
-    const sagms_plan& p = b->plan;
-    MixedLaunch L{p.tile_frames, p.waves_per_block, p.blocks_per_cu, p.reg_budget};
-    return launch_segments(b->segs.data() + s0, s1 - s0, tier, L, b->num_cu, b->mt,
-                           b->d_queues + (size_t)tier * kMaxQueues * kQueueStride, &b->occupancy, st);
-}
-
 int enqueue(Batch* b, hipStream_t st) {
-    const sagms_plan& p = b->plan;
-    if (p.kind == SAGMS_PLAN_PER_CODE) {
-        for (int s = 0; s < b->nseg; ++s) {
-            if (b->segs[s].a.nframes == 0) continue;
-            DecodeArgs a = b->segs[s].a;
-            a.frames_per_wave = p.tile_frames;
-            int rc = launch_decode(b->shape[s], false, b->mt, a, st);
-            if (rc) return rc;
-        }
-        return SAGMS_OK;
-    }
-    if (p.kind == SAGMS_PLAN_SINGLE) return launch_group(b, 0, b->nseg, b->tier.front(), st);
-    for (int s0 = 0; s0 < b->nseg;) {
-        int s1 = s0;
-        while (s1 < b->nseg && b->tier[s1] == b->tier[s0]) ++s1;
-        int rc = launch_group(b, s0, s1, b->tier[s0], st);
-        if (rc) return rc;
-        s0 = s1;
-    }
-    return SAGMS_OK;
+    return enqueue_segments(b->set, b->plan, b->mt, b->num_cu, b->d_queues, &b->occupancy, st);
 }
 
 int check_device(const Batch* b) {
@@ -168,64 +227,18 @@ extern "C" {
 int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_decoder_cfg* cfg, sagms_batch* out) {
     if (!out) return fail(SAGMS_EINVAL, "out is null");
     *out = nullptr;
-    if (!segs) return fail(SAGMS_EINVAL, "segs is null");
-    if (nseg < 1 || nseg > kMaxSegments) return fail(SAGMS_EINVAL, "nseg must lie in [1, %d]", kMaxSegments);
-    int rc = check_cfg(cfg);
-    if (rc) return rc;
-    if (cfg->kind == SAGMS_BP) return fail(SAGMS_EUNSUPPORTED, "batches run MS, SMS and SAGMS only");
-    if (cfg->schedule != SAGMS_FLOODING) return fail(SAGMS_EUNSUPPORTED, "batches run the flooding schedule only");
-    for (int s = 0; s < nseg; ++s) {
-        const sagms_segment& x = segs[s];
-        Graph* g = reinterpret_cast<Graph*>(x.graph);
-        if (!g) return fail(SAGMS_EINVAL, "segment %d: null graph", s);
-        if (!g->shape_ok) return fail(SAGMS_EUNSUPPORTED, "segment %d: no decode kernel fits the code", s);
-        if (shape_index(g->shape) < 0) return fail(SAGMS_EUNSUPPORTED, "segment %d: shape not compiled", s);
-        if (x.nframes < 0) return fail(SAGMS_EINVAL, "segment %d: nframes must be >= 0", s);
-        if (x.nframes > 0 && (!x.synd || !x.llr0 || !x.ehat || !x.iters || !x.converged))
-            return fail(SAGMS_EINVAL, "segment %d: null buffer", s);
-    }
     Batch* b = new Batch();
+    int rc = prepare_segments(segs, nseg, cfg, true, &b->set);
+    if (rc) {
+        destroy(b);
+        return rc;
+    }
     b->cfg = *cfg;
     b->mt = cfg->msg_precision;
-    b->nseg = nseg;
     b->plan = sagms_plan{SAGMS_PLAN_SINGLE, kMixedTileFrames, 4, 0, 0, 0};
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device);
-    if (e != hipSuccess) {
-        destroy(b);
-        return hip_fail(e, "hipGetDevice / hipDeviceGetAttribute");
-    }
-    // launch order: largest register tier first, then the most lane slots per
-    // round (the most expensive frames first), then the caller's order
-    std::vector<int> order(nseg);
-    std::iota(order.begin(), order.end(), 0);
-    auto cost = [&](int s) {
-        const DecodeShape& sh = reinterpret_cast<Graph*>(segs[s].graph)->shape;
-        return sh.cpl * sh.dc + sh.vpl * sh.dv;
-    };
-    auto tier = [&](int s) { return mixed_tier_of_shape(shape_index(reinterpret_cast<Graph*>(segs[s].graph)->shape)); };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        if (tier(x) != tier(y)) return tier(x) > tier(y);
-        return cost(x) > cost(y);
-    });
-    for (int s : order) {
-        const sagms_segment& x = segs[s];
-        Graph* g = reinterpret_cast<Graph*>(x.graph);
-        DeviceTables* t = nullptr;
-        rc = upload_tables(g, &t);
-        if (rc) {
-            destroy(b);
-            return rc;
-        }
-        MixedSegment ms{};
-        ms.a = decode_args(g, t, gain_law(cfg), x.synd, x.llr0, x.nframes, x.ehat, x.iters, x.converged, x.posterior,
-                           cfg->lmax, 0);
-        ms.shape = shape_index(g->shape);
-        b->segs.push_back(ms);
-        b->tier.push_back(tier(s));
-        b->shape.push_back(g->shape);
-    }
-    e = hipMalloc(&b->d_queues, sizeof(uint32_t) * kNumMixedTiers * kMaxQueues * kQueueStride);
+    if (e == hipSuccess) e = hipMalloc(&b->d_queues, sizeof(uint32_t) * kScratchWords);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         destroy(b);
@@ -238,7 +251,7 @@ int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_deco
 int sagms_batch_set_plan(sagms_batch bh, const sagms_plan* plan) {
     Batch* b = reinterpret_cast<Batch*>(bh);
     if (!b) return fail(SAGMS_EINVAL, "null batch");
-    int rc = check_plan(b, plan);
+    int rc = check_plan(plan);
     if (rc) return rc;
     drop_graph(b);
     b->plan = *plan;
@@ -272,7 +285,8 @@ int sagms_batch_instantiate(sagms_batch bh) {
     if (rc) return rc;
     drop_graph(b);
     if (b->plan.kind != SAGMS_PLAN_PER_CODE)
-        for (int t : b->tier) {  // occupancy queries stay outside the capture
+        for (int i = 0; i < b->set.nseg; ++i) {  // occupancy queries stay outside the capture
+            const int t = b->set.tier[i];
             int n = 0;
             rc = blocks_per_cu(b, t, &n);
             if (rc) return rc;
@@ -315,24 +329,26 @@ int sagms_batch_tune(sagms_batch bh, void* stream, int32_t reps, sagms_tune_resu
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     std::vector<sagms_plan> cands;
     const int tiles[] = {4, 8, 16, 32};
-    const int multi_tier = std::count(b->tier.begin(), b->tier.end(), b->tier.front()) != b->nseg;
+    const int* tiers = b->set.tier;
+    const int nseg = b->set.nseg;
+    const int multi_tier = std::count(tiers, tiers + nseg, tiers[0]) != nseg;
     bool tight = false;  // a tight budget exists for some tier of the batch
-    for (int t : b->tier) tight = tight || mixed_has_budget(t, 1);
+    for (int i = 0; i < nseg; ++i) tight = tight || mixed_has_budget(tiers[i], 1);
     for (int kind : {SAGMS_PLAN_SINGLE, SAGMS_PLAN_TIERED}) {
         if (kind == SAGMS_PLAN_TIERED && !multi_tier) continue;
         for (int budget : {0, 1}) {
-            if (budget == 1 && (kind == SAGMS_PLAN_SINGLE ? !mixed_has_budget(b->tier.front(), 1) : !tight))
+            if (budget == 1 && (kind == SAGMS_PLAN_SINGLE ? !mixed_has_budget(tiers[0], 1) : !tight))
                 continue;
             for (int wpb : {1, 2, 4})
                 for (int tf : tiles) {
                     // a waves-per-block value that every launched tier halves is a duplicate
                     bool dup = true;
-                    for (int t : b->tier)
-                        if ((kind == SAGMS_PLAN_TIERED || t == b->tier.front()) && mixed_waves_of(t, wpb) == wpb)
+                    for (int i = 0; i < nseg; ++i)
+                        if ((kind == SAGMS_PLAN_TIERED || tiers[i] == tiers[0]) && mixed_waves_of(tiers[i], wpb) == wpb)
                             dup = false;
                     if (dup) continue;
                     sagms_plan p{kind, tf, wpb, 0, budget, 0};
-                    if (check_plan(b, &p) == SAGMS_OK) cands.push_back(p);
+                    if (check_plan(&p) == SAGMS_OK) cands.push_back(p);
                 }
         }
     }
@@ -391,6 +407,27 @@ int sagms_batch_tune(sagms_batch bh, void* stream, int32_t reps, sagms_tune_resu
     if (count) *count = std::min(n, cap);
     if (best) *best = best_plan;
     return SAGMS_OK;
+}
+
+int sagms_decode_segments(const sagms_segment* segs, int32_t nseg, const sagms_decoder_cfg* cfg,
+                          const sagms_plan* plan, void* stream) {
+    SegmentSet set;
+    int rc = prepare_segments(segs, nseg, cfg, false, &set);
+    if (rc) return rc;
+    const sagms_plan p = plan ? *plan : sagms_plan{SAGMS_PLAN_SINGLE, kMixedTileFrames, 4, 0, 0, 0};
+    rc = check_plan(&p);
+    if (rc) return rc;
+    uint32_t* queues = nullptr;
+    rc = scratch_queues(&queues);
+    if (rc) return rc;
+    int dev = 0, num_cu = 0;
+    SAGMS_HIP(hipGetDevice(&dev));
+    SAGMS_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    // resident blocks per CU, queried once per key and process (fixed table)
+    static std::mutex mu;
+    static OccupancyCache occ[kMaxDevices];
+    std::lock_guard<std::mutex> lock(mu);
+    return enqueue_segments(set, p, cfg->msg_precision, num_cu, queues, &occ[dev], reinterpret_cast<hipStream_t>(stream));
 }
 
 int sagms_batch_destroy(sagms_batch bh) {

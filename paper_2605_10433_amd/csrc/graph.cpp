@@ -335,7 +335,9 @@ int upload_tables(Graph* g, DeviceTables** out) {
     std::lock_guard<std::mutex> lock(g->mu);
     DeviceTables* t = &g->dev[dev];
     if (!t->ready) {
-        const int rc = upload_locked(g, t);
+        int rc = scratch_setup();  // the device's queue counters for sagms_decode_segments
+        if (rc) return rc;
+        rc = upload_locked(g, t);
         if (rc) {
             free_tables(t);
             return rc;

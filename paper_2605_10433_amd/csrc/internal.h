@@ -239,9 +239,12 @@ int mixed_budget_of(int tier, int requested);
 // LDS slices fit 64 KiB.
 int mixed_waves_of(int tier, int requested);
 
-// Resident blocks per CU of the mixed kernels, queried once per key.
+// Resident blocks per CU of the mixed kernels, queried once per (tier,
+// register budget, message format, waves per block); a fixed table, so that
+// lookups never allocate.
 struct OccupancyCache {
-    std::map<std::tuple<int, int, int, int>, int> blocks;
+    int blocks[kNumMixedTiers][2][3][5];
+    OccupancyCache();
     int get(int tier, int budget, int mt, int waves_per_block, int* out);
 };
 
@@ -254,6 +257,38 @@ struct MixedLaunch {
 // and by the number of tiles); queues = this launch's own counter block.
 int launch_segments(const MixedSegment* segs, int nseg, int tier, const MixedLaunch& p, int num_cu, int mt,
                     uint32_t* queues, OccupancyCache* occ, hipStream_t st);
+
+// The segments of a mixed-code decode in launch order (register tier
+// descending, then lane slots per round descending, then the caller's
+// order), with their kernel arguments.  Fixed size: no allocation.
+struct SegmentSet {
+    int nseg = 0;
+    MixedSegment segs[kMaxSegments];
+    int tier[kMaxSegments];
+    DecodeShape shape[kMaxSegments];
+};
+
+// Checks the segments and the configuration (MS, SMS or SAGMS, flooding)
+// and fills *out.  upload: copy missing graph tables to the current device
+// (set-up calls); otherwise a graph without tables there is an error.
+int prepare_segments(const sagms_segment* segs, int nseg, const sagms_decoder_cfg* cfg, bool upload,
+                     SegmentSet* out);
+// Checks a launch plan (SAGMS_EINVAL).
+int check_plan(const sagms_plan* p);
+// Enqueues one decode of every segment under plan p: PER_CODE as single-code
+// decode launches, SINGLE / TIERED as persistent launches whose tier t uses
+// the kMaxQueues counters at queues + t * kMaxQueues * kQueueStride.
+int enqueue_segments(const SegmentSet& set, const sagms_plan& p, int mt, int num_cu, uint32_t* queues,
+                     OccupancyCache* occ, hipStream_t st);
+
+// Queue counters of sagms_decode_segments: a static device array of
+// kNumMixedTiers * kMaxQueues * kQueueStride words (mixed.hip).
+constexpr size_t kScratchWords = (size_t)kNumMixedTiers * kMaxQueues * kQueueStride;
+// Takes the array's device address on the current device (once per device;
+// called from upload_tables, which runs with the device current).
+int scratch_setup();
+// The array's device address on the current device, set up before.
+int scratch_queues(uint32_t** out);
 
 
 struct SampleArgs {

@@ -10,9 +10,45 @@
 // them only when its next tile belongs to another segment.  Each frame is
 // decoded by the same per-frame code as the single-code kernel, so results
 // do not depend on the mix, the tiling or the order in which tiles run.
+#include <mutex>
+
 #include "decode_core.h"
 
 namespace sagms {
+
+// Queue counters of sagms_decode_segments, the entry point that allocates
+// nothing: kNumMixedTiers blocks of kMaxQueues counters (16 KiB), one copy on
+// every device the library runs on, held until the process ends.  Host code
+// never uses the array's name as an address: it uses the device address that
+// hipGetSymbolAddress returned for the current device (scratch_queues).
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+static std::mutex g_scratch_mu;
+static uint32_t* g_scratch_ptr[kMaxDevices];
+
+int scratch_setup() {
+    int dev = 0;
+    SAGMS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SAGMS_EUNSUPPORTED, "device index %d too large", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return SAGMS_OK;
+    void* ptr = nullptr;
+    SAGMS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SAGMS_EHIP, "hipGetSymbolAddress returned a null address for the queue counters");
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(ptr);
+    return SAGMS_OK;
+}
+
+int scratch_queues(uint32_t** out) {
+    int dev = 0;
+    SAGMS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SAGMS_EUNSUPPORTED, "device index %d too large", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev])
+        return fail(SAGMS_EINVAL, "no graph has been uploaded to device %d (sagms_graph_upload sets it up)", dev);
+    *out = g_scratch_ptr[dev];
+    return SAGMS_OK;
+}
 
 constexpr int kMixedMaxWavesPerBlock = 4;
 
