@@ -211,7 +211,8 @@ int sagms_derive_gains(double l0, int32_t dc, double ratio, double eta, sagms_de
  * is X if u < T_X, Y if u < T_Y, Z if u < T_Z, else I.
  * Outputs (device, packed): ex, ez [nframes][words_n] the X and Z parts
  * (ez may be NULL to skip it), synd [nframes][words_m] = H e_x (mod 2).
- * 0 <= p < 1; nframes >= 0 (0 is a no-op). */
+ * 0 <= p < 1; 0 <= nframes <= 2^31 - 1 (0 is a no-op; SAGMS_EINVAL outside,
+ * checked before any device work, as for every device call). */
 int sagms_gen_errors(sagms_graph g, uint64_t seed, uint32_t stream_id, uint64_t frame0, int64_t nframes,
                      double p, uint64_t* ex, uint64_t* ez, uint64_t* synd, void* stream);
 
@@ -231,7 +232,7 @@ int sagms_gen_errors(sagms_graph g, uint64_t seed, uint32_t stream_id, uint64_t 
  * its graph's check order (see the two graph builders) and v2c =
  * posterior - c2v; the BP CN runs in FP64.
  * Per-frame results do not depend on nframes, the batch split or the
- * stream.  nframes >= 0. */
+ * stream.  0 <= nframes <= 2^31 - 1. */
 int sagms_decode(sagms_graph g, const uint64_t* synd, const float* llr0, const sagms_decoder_cfg* cfg,
                  int64_t nframes, uint64_t* ehat, int32_t* iters, uint8_t* converged, void* stream);
 

@@ -13,6 +13,13 @@ constexpr int kSampleFramesPerWave = 4;
 
 namespace sagms {
 
+int check_frames(int64_t nframes) {
+    if (nframes < 0) return fail(SAGMS_EINVAL, "nframes must be >= 0");
+    if (nframes > kMaxFramesPerCall)
+        return fail(SAGMS_EINVAL, "too many frames for one call: %lld (at most 2^31 - 1)", (long long)nframes);
+    return SAGMS_OK;
+}
+
 int check_cfg(const sagms_decoder_cfg* c) {
     if (!c) return fail(SAGMS_EINVAL, "cfg is null");
     if (c->kind < SAGMS_MS || c->kind > SAGMS_BP) return fail(SAGMS_EINVAL, "unknown decoder kind %d", c->kind);
@@ -84,13 +91,14 @@ int sagms_gen_errors(sagms_graph gh, uint64_t seed, uint32_t stream_id, uint64_t
                      uint64_t* ex, uint64_t* ez, uint64_t* synd, void* stream) {
     Graph* g = reinterpret_cast<Graph*>(gh);
     if (!g) return fail(SAGMS_EINVAL, "null graph");
-    if (nframes < 0) return fail(SAGMS_EINVAL, "nframes must be >= 0");
+    int rc = check_frames(nframes);
+    if (rc) return rc;
     if (!(p >= 0.0 && p < 1.0)) return fail(SAGMS_EINVAL, "p must lie in [0, 1)");
     if (nframes == 0) return SAGMS_OK;
     if (!ex || !synd) return fail(SAGMS_EINVAL, "ex and synd must not be null");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     DeviceTables* t = nullptr;
-    int rc = device_tables(g, &t);
+    rc = device_tables(g, &t);
     if (rc) return rc;
     SampleArgs a{};
     a.cols = t->cols;
@@ -127,7 +135,8 @@ int sagms_decode_soft(sagms_graph gh, const uint64_t* synd, const float* llr0, c
     if (!g) return fail(SAGMS_EINVAL, "null graph");
     int rc = check_cfg(cfg);
     if (rc) return rc;
-    if (nframes < 0) return fail(SAGMS_EINVAL, "nframes must be >= 0");
+    rc = check_frames(nframes);
+    if (rc) return rc;
     if (!g->shape_ok)
         return fail(SAGMS_EUNSUPPORTED, "no decode kernel fits m=%d n=%d dc=%d dv=%d", g->m, g->n, g->dc_max, g->dv_max);
     if (nframes == 0) return SAGMS_OK;
@@ -149,12 +158,13 @@ int sagms_judge(sagms_graph gh, const uint64_t* ex, const uint64_t* ehat, const 
     Graph* g = reinterpret_cast<Graph*>(gh);
     if (!g) return fail(SAGMS_EINVAL, "null graph");
     if (!g->have_other) return fail(SAGMS_EINVAL, "the judge needs a graph built with the other check matrix");
-    if (nframes < 0) return fail(SAGMS_EINVAL, "nframes must be >= 0");
+    int rc = check_frames(nframes);
+    if (rc) return rc;
     if (nframes == 0) return SAGMS_OK;
     if (!ex || !ehat || !converged || !iters || !counters) return fail(SAGMS_EINVAL, "null buffer");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     DeviceTables* t = nullptr;
-    int rc = device_tables(g, &t);
+    rc = device_tables(g, &t);
     if (rc) return rc;
     JudgeArgs a{};
     a.ex = ex;

@@ -91,7 +91,8 @@ int prepare_segments(const sagms_segment* segs, int nseg, const sagms_decoder_cf
         if (!g) return fail(SAGMS_EINVAL, "segment %d: null graph", s);
         if (!g->shape_ok) return fail(SAGMS_EUNSUPPORTED, "segment %d: no decode kernel fits the code", s);
         if (shape_index(g->shape) < 0) return fail(SAGMS_EUNSUPPORTED, "segment %d: shape not compiled", s);
-        if (x.nframes < 0) return fail(SAGMS_EINVAL, "segment %d: nframes must be >= 0", s);
+        if (x.nframes < 0 || x.nframes > kMaxFramesPerCall)
+            return fail(SAGMS_EINVAL, "segment %d: nframes must lie in [0, 2^31 - 1]", s);
         if (x.nframes > 0 && (!x.synd || !x.llr0 || !x.ehat || !x.iters || !x.converged))
             return fail(SAGMS_EINVAL, "segment %d: null buffer", s);
     }

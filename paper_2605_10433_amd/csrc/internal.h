@@ -25,6 +25,12 @@ int hip_fail(hipError_t e, const char* what);
 
 constexpr int kMaxDevices = 64;
 constexpr int kMaxN = 4096;
+// Frames per device call: at most 2^31 - 1, which keeps every launch's grid
+// (at most one wavefront per frame) within 2^31 - 1 blocks.
+constexpr int64_t kMaxFramesPerCall = 0x7fffffffLL;
+// SAGMS_OK, or SAGMS_EINVAL for nframes < 0 or > kMaxFramesPerCall (host
+// check, before any device work).
+int check_frames(int64_t nframes);
 
 // ---- decode kernel shapes ---------------------------------------------
 // One wavefront decodes one frame at a time.  Lane l owns checks l + 64 k

@@ -142,6 +142,35 @@ def test_gen_errors_and_judge_argument_checks():
     assert L.sagms_judge(g2._h, None, None, None, None, 4, None, None, None) == sagms.EINVAL   # no H_other
 
 
+def test_more_frames_than_one_call_allows_are_refused_on_the_host():
+    """Every device call refuses more than 2^31 - 1 frames (which keeps every
+    grid within 2^31 - 1 blocks) with SAGMS_EINVAL, checked before anything
+    touches a device: here on a host without one, with buffer pointers that
+    are never dereferenced (a decode of 2^50 frames, every launch shape; the
+    sampler; the judge; a mixed-batch segment)."""
+    L = sagms.lib()
+    g = sagms.Graph.gb(*workloads.code("G63"))
+    fake = ctypes.c_void_p(0x1000)
+    for huge in (1 << 31, 1 << 50):
+        assert L.sagms_gen_errors(g._h, 1, 0, 0, huge, 0.05, fake, fake, fake, None) == sagms.EINVAL
+        assert "too many frames" in L.sagms_last_error().decode()
+        for fpw in (0, 1, 1024):
+            cfg = sagms.decoder_config("sagms", frames_per_wave=fpw)
+            assert L.sagms_decode(g._h, fake, fake, ctypes.byref(cfg), huge, fake, fake, fake, None) == sagms.EINVAL
+            assert "too many frames" in L.sagms_last_error().decode()
+        assert L.sagms_judge(g._h, fake, fake, fake, fake, huge, fake, fake, None) == sagms.EINVAL
+        assert "too many frames" in L.sagms_last_error().decode()
+        seg = (sagms.Segment * 1)()
+        seg[0].graph, seg[0].nframes = g._h.value, huge
+        seg[0].synd = seg[0].llr0 = seg[0].ehat = seg[0].iters = seg[0].converged = 0x1000
+        out = ctypes.c_void_p()
+        cfg = sagms.decoder_config("sagms")
+        assert L.sagms_batch_create(ctypes.cast(seg, ctypes.c_void_p), 1, ctypes.byref(cfg),
+                                    ctypes.byref(out)) == sagms.EINVAL
+        assert L.sagms_decode_segments(ctypes.cast(seg, ctypes.c_void_p), 1, ctypes.byref(cfg), None,
+                                       None) == sagms.EINVAL
+
+
 @pytest.mark.parametrize("p", workloads.P_GRID + [0.001, 0.3])
 def test_prior_llr_matches_oracle(p):
     assert sagms.prior_llr(p) == np.float32(channel.prior_llr(p))

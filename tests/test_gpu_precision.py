@@ -1,14 +1,27 @@
-"""Reduced-precision messages on the mixed-code workload, against FP64.
+"""Message formats on the mixed-code workload, against the FP64 oracle.
 
-For every code of the mix and p in {0.03, 0.05}: the first frames of the
-mix's Philox streams are decoded on the GPU with FP32, FP16 and INT6
-messages (SAGMS) and by the FP64 oracle.  Recorded: each format's FER and
-the fraction of frames whose hard decision differs from FP64.  Asserted:
-FP32 and FP16 agree with FP64 on nearly every frame; INT6's FER lies within
-the Wilson interval of the FP64 FER on the same frames, widened by the
-coarse grid's own effect (checked only where FP64 converges on most frames).
-With SAGMS_RECORD_DIR set, the records are written to precision_mix.json
-in that folder.
+For every code of the mix and p in {0.03, 0.05}: the first FRAMES frames of
+the mix's Philox streams are decoded on the GPU with FP32, FP16 and INT6
+messages (SAGMS) and by the FP64 oracle (FP64 prior) in a pool of host
+processes.  Recorded per format: FER with its 95 % Wilson interval, the
+fraction of frames whose hard decision differs from FP64 (all frames, and
+frames converged in both), and the paired failure counts b (FP64 fails, the
+format does not) and c (the reverse).
+
+Asserted:
+* FP32 and FP16: the FER lies in the FP64 FER's Wilson interval and the
+  paired difference c - b lies within 3 sigma of 0 (|c - b| <= 3 sqrt(b + c),
+  the normal approximation of the sign test on the discordant frames);
+* every format: among frames that converge in both, the hard decision
+  differs from FP64's in at most 1 % (they reach the same syndrome-matching
+  estimate).
+INT6 (a sign and 6-bit magnitude on a 1/4 grid) is a different decoder
+whose FER is reported, not matched: on the weight-3 l = 255 code at p = 0.05
+it fails measurably more often than FP64.
+
+FRAMES = 2^14 by default (about a minute of oracle time on 16 processes);
+2^16 with SAGMS_PRECISION_FULL=1.  With SAGMS_RECORD_DIR set, the records are
+written to precision_mix.json in that folder.
 """
 import json
 import os
@@ -19,11 +32,12 @@ import pytest
 torch = pytest.importorskip("torch")
 import paper_2605_10433_amd as sagms  # noqa: E402
 import workloads  # noqa: E402
-from oracle import channel, codes, decoders, judge, stats  # noqa: E402
+from oracle import stats  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-FRAMES = 512
+FRAMES = 1 << (16 if os.environ.get("SAGMS_PRECISION_FULL") == "1" else 14)
+CHUNK = 512
 RECORDS = []
 
 
@@ -38,45 +52,53 @@ def dev():
             json.dump(RECORDS, fh, indent=1)
 
 
+def oracle_fp64(pool, name, idx, p):
+    import sweep_oracle  # tests/helpers, on the path of the pool's workers
+    tasks = [dict(code=name, seed=workloads.MIX_SEED, stream=workloads.mix_stream(idx, p), kind="sagms",
+                  kw=dict(workloads.SAGMS_PARAMS), p=p, frame0=f0, nframes=min(CHUNK, FRAMES - f0),
+                  lmax=workloads.MIX_LMAX, arith="fp64") for f0 in range(0, FRAMES, CHUNK)]
+    parts = sorted(pool.imap_unordered(sweep_oracle.decode_point, tasks), key=lambda r: r["frame0"])
+    return {k: np.concatenate([r[k] for r in parts]) for k in ("synd", "ehat", "iters", "converged", "fail")}
+
+
 @pytest.mark.parametrize("p", workloads.PRECISION_P)
 @pytest.mark.parametrize("idx", range(len(workloads.MIX_CODES)))
-def test_formats_against_fp64(dev, idx, p):
+def test_formats_against_fp64(dev, oracle_pool, idx, p):
     name = workloads.MIX_CODES[idx]
-    l, a, b = workloads.code(name)
-    hx, hz = codes.gb_matrices(l, a, b)
-    lz = codes.logical_basis(hz, hx)
-    sid = workloads.mix_stream(idx, p)
-    ex, _ = channel.sample_paulis(workloads.MIX_SEED, sid, 0, FRAMES, 2 * l, p)
-    synd = channel.syndrome(hz, ex)
-    ref = decoders.decode(decoders.TannerGraph(hz, codes.gb_var_checks(l, a, b)), synd,
-                          np.full(2 * l, channel.prior_llr(p)),
-                          decoders.DecoderParams(kind="sagms", lmax=workloads.MIX_LMAX, **workloads.SAGMS_PARAMS),
-                          "fp64")
-    fer64 = judge.judge_logical(lz, ex, ref.ehat, ref.converged)
-    g = sagms.Graph.gb(l, a, b)
-    synd_dev = torch.from_numpy(channel.pack(synd).view(np.int64)).to(dev)
+    print("precision", name, p, FRAMES, flush=True)
+    ref = oracle_fp64(oracle_pool, name, idx, p)
+    g = sagms.Graph.gb(*workloads.code(name))
+    buf = sagms.frame_buffers(g, FRAMES, device=dev)
+    sagms.gen_errors(g, workloads.MIX_SEED, workloads.mix_stream(idx, p), 0, FRAMES, p, buf["ex"], None, buf["synd"])
     llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
-    rec = {"code": name, "p": p, "frames": FRAMES, "fp64_fer": float(fer64.mean()),
-           "fp64_converged": float(ref.converged.mean())}
+    torch.cuda.synchronize()
+    assert (buf["synd"].cpu().numpy().view(np.uint64) == ref["synd"]).all()
+    f64 = int(ref["fail"].sum())
+    lo64, hi64 = stats.wilson(f64, FRAMES)
+    rec = {"code": name, "p": p, "frames": FRAMES, "fp64_fer": f64 / FRAMES, "fp64_fer_wilson95": [lo64, hi64],
+           "fp64_converged": float(ref["converged"].mean())}
     for fmt in ("fp32", "fp16", "int6"):
-        print("precision", name, p, fmt, flush=True)
         cfg = sagms.decoder_config("sagms", lmax=workloads.MIX_LMAX, precision=fmt, **workloads.SAGMS_PARAMS)
-        out = sagms.frame_buffers(g, FRAMES, device=dev)
-        sagms.decode(g, synd_dev, llr, cfg, out["ehat"], out["iters"], out["converged"])
+        counters = torch.zeros(2, dtype=torch.int64, device=dev)
+        sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
+        sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters, fail=buf["fail"])
         torch.cuda.synchronize()
-        ehat = channel.unpack(out["ehat"].cpu().numpy().view(np.uint64), g.n)
-        conv = out["converged"].cpu().numpy().astype(bool)
-        fail = judge.judge_logical(lz, ex, ehat, conv)
-        differ = (ehat != ref.ehat).any(axis=1)
+        ehat = buf["ehat"].cpu().numpy().view(np.uint64)
+        conv = buf["converged"].cpu().numpy().astype(bool)
+        fail = buf["fail"].cpu().numpy().astype(bool)
+        differ = (ehat != ref["ehat"]).any(axis=1)
+        both = conv & ref["converged"]
+        b = int((ref["fail"] & ~fail).sum())
+        c = int((fail & ~ref["fail"]).sum())
         lo, hi = stats.wilson(int(fail.sum()), FRAMES)
+        hd_both = float(differ[both].mean()) if both.any() else 0.0
         rec[fmt] = {"fer": float(fail.mean()), "fer_wilson95": [lo, hi], "hd_differs_from_fp64": float(differ.mean()),
-                    "mean_iters": float(out["iters"].float().mean().item())}
+                    "hd_differs_converged_both": hd_both,
+                    "fp64_only_failures": b, "format_only_failures": c,
+                    "mean_iters": float(buf["iters"].float().mean().item())}
+        assert hd_both <= 0.01, (name, p, fmt, hd_both)
         if fmt in ("fp32", "fp16"):
-            # both keep the FP64 trajectory on converging frames up to rounding
-            both = conv & ref.converged
-            assert (differ & both).mean() <= (0.02 if fmt == "fp32" else 0.05), (name, p, fmt, (differ & both).mean())
-        elif ref.converged.mean() > 0.9:
-            lo64, hi64 = stats.wilson(int(fer64.sum()), FRAMES)
-            assert lo64 - 0.02 <= fail.mean() <= hi64 + 0.02, (name, p, fmt, fail.mean(), lo64, hi64)
+            assert lo64 <= fail.mean() <= hi64, (name, p, fmt, float(fail.mean()), lo64, hi64)
+            assert abs(c - b) <= 3.0 * np.sqrt(b + c), (name, p, fmt, b, c)
     RECORDS.append(rec)
     print(json.dumps(rec), flush=True)

@@ -3,7 +3,9 @@
 Each served request's outputs must equal, bit for bit, the same syndromes
 decoded alone by sagms_decode (one call for that request only), for traces
 that keep several launches in flight, mix five codes of three register
-classes and exercise the frame budget, deadlines and manual progress.
+classes and exercise the frame budget, deadlines and manual progress; and
+sampled served frames of every code equal the CPU oracle's decode of the
+same syndromes (FP32 and FP16 messages).
 """
 import numpy as np
 import pytest
@@ -11,6 +13,9 @@ import pytest
 torch = pytest.importorskip("torch")
 import paper_2605_10433_amd as sagms  # noqa: E402
 import workloads  # noqa: E402
+from oracle import channel  # noqa: E402
+from oracle import codes as ocodes  # noqa: E402
+from oracle import decoders  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +90,27 @@ def check_alone(graphs, cfg, dev, pools, outs, slices, picks):
         assert (outs[c]["conv"][lo:lo + nf] == cv).all(), ("converged", i, c)
 
 
+def check_oracle(graphs, precision, pools, outs, per_code=48):
+    """Sampled served frames of every code against the oracle's decode of the
+    same syndromes in the matching message format."""
+    for c, name in enumerate(workloads.SERVE_CODES):
+        nf = len(pools[c])
+        if nf == 0:
+            continue
+        idx = np.unique(np.linspace(0, nf - 1, min(per_code, nf)).astype(int))
+        l, a, b = workloads.code(name)
+        hz = ocodes.gb_matrices(l, a, b)[1]
+        tg = decoders.TannerGraph(hz, ocodes.gb_var_checks(l, a, b))
+        s = channel.unpack(pools[c][idx], tg.m)
+        r = decoders.decode(tg, s, np.full(tg.n, sagms.prior_llr(workloads.SERVE_P), np.float32),
+                            decoders.DecoderParams(kind="sagms", lmax=workloads.SERVE_LMAX,
+                                                   **workloads.SAGMS_PARAMS), precision)
+        assert (outs[c]["ehat"][idx] == channel.pack(r.ehat)).all(), (name, "ehat")
+        assert (outs[c]["iters"][idx] == r.iters).all(), (name, "iters")
+        assert (outs[c]["conv"][idx] == r.converged).all(), (name, "converged")
+        say("served frames of", name, "against the oracle:", len(idx), "equal")
+
+
 def check_pools(graphs, cfg, dev, pools, outs):
     """All served frames of a code against one sagms_decode over its pool."""
     for c, g in enumerate(graphs):
@@ -108,6 +134,7 @@ def test_served_results_equal_alone(dev, codes, precision):
     assert (done["id"] == np.arange(len(reqs))).all()
     assert (done["done_us"] >= done["admit_us"]).all() and (done["admit_us"] >= done["submit_us"]).all()
     check_pools(graphs, cfg, dev, pools, outs)
+    check_oracle(graphs, precision, pools, outs)
     rng = np.random.default_rng(1)
     check_alone(graphs, cfg, dev, pools, outs, slices, rng.choice(len(reqs), 25, replace=False))
     assert srv.pending() == (0, 0, 0)

@@ -1,29 +1,31 @@
-"""Parity over the whole l = 63 noise sweep, at sweep scale (opt-in).
+"""Parity over the whole l = 63 noise sweep.
 
 Every point of the sweep: p = 0.02 .. 0.10, frames of seed 1 and stream =
 index of p, l_max = 100, decoded end to end by libsagms (Philox sampling,
 syndromes, decoding, judge) and by the oracle in a pool of host processes.
 
 * Every decoder of the sweep (MS, SMS with alpha = 0.5 / 0.625 / 0.75 /
-  0.875, SAGMS with the Section V parameters) on the first 2^16 frames of
-  each point, frame by frame against the oracle's FP32 mode: syndromes,
-  hard decisions, round counts, flags, posteriors and verdicts bit-exact.
-  BP (transcendental check rule): hard decision and round count agree on
-  >= 97 % of frames, posteriors within 1e-4 relative on those.
-* SAGMS on all 2^20 frames of each point against the FP64 oracle: each FER
-  lies in the other's 95 % Wilson interval, and frames that converge in
-  both agree in their hard decision on >= 99 %.
+  0.875, SAGMS with the Section V parameters) on the first FRAMES_EXACT
+  frames of each point, frame by frame against the oracle's FP32 mode:
+  syndromes, hard decisions, round counts, flags, posteriors and verdicts
+  bit-exact.  BP (transcendental check rule): hard decision and round count
+  agree on >= 97 % of frames, posteriors within 1e-4 relative on those
+  (its per-round FP64 bar is in test_gpu_parity.py).
+* SAGMS on the first FRAMES_FER frames of each point against the FP64
+  oracle: each FER lies in the other's 95 % Wilson interval, and frames
+  that converge in both agree in their hard decision on >= 99 %.
 * SAGMS with FP16 and INT6 messages, and MS / SMS / SAGMS with the layered
-  schedule, on the first 2^16 frames of each point, frame by frame against
-  the oracle's matching mode.
+  schedule, on the first FRAMES_REDUCED frames of each point, frame by frame
+  against the oracle's matching mode.
 
-Several minutes of oracle time even on 16 host processes, so it runs only
-with SAGMS_SWEEP_PARITY=1 (workers: SAGMS_ORACLE_PROCS, default the host's
-cores up to 16).  Each point prints one line starting with "sweep-parity".
+Sizes: by default 2^12 / 2^16 / 2^10 frames (about a minute of oracle time
+on 16 host processes); with SAGMS_SWEEP_PARITY=1 the sweep-scale sizes
+2^16 / 2^20 / 2^16 (several minutes).  Workers: SAGMS_ORACLE_PROCS, default
+the host's cores up to 16.  Each point prints one line starting with
+"sweep-parity".
 """
 import json
 import os
-import sys
 import time
 
 import numpy as np
@@ -34,16 +36,12 @@ import paper_2605_10433_amd as sagms  # noqa: E402
 import workloads  # noqa: E402
 from oracle import stats  # noqa: E402
 
-sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "helpers"))
+pytestmark = pytest.mark.gpu
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("SAGMS_SWEEP_PARITY") != "1",
-                                 reason="sweep-scale oracle run (minutes on a process pool); "
-                                        "set SAGMS_SWEEP_PARITY=1")]
-
-FRAMES_EXACT = 1 << 16
-FRAMES_FER = 1 << 20
-CHUNK = 4096
+FULL = os.environ.get("SAGMS_SWEEP_PARITY") == "1"
+FRAMES_EXACT = 1 << (16 if FULL else 12)
+FRAMES_FER = 1 << (20 if FULL else 16)
+FRAMES_REDUCED = 1 << (16 if FULL else 10)
 LMAX = workloads.SWEEP_LMAX
 DECODERS = ([("ms", {})] + [("sms", dict(alpha=a)) for a in workloads.SMS_ALPHAS] +
             [("sagms", dict(workloads.SAGMS_PARAMS)), ("bp", {})])
@@ -61,11 +59,8 @@ def dev():
 
 
 @pytest.fixture(scope="module")
-def pool():
-    import multiprocessing as mp
-    procs = int(os.environ.get("SAGMS_ORACLE_PROCS", min(16, os.cpu_count() or 1)))
-    with mp.get_context("spawn").Pool(procs) as pl:
-        yield pl
+def pool(oracle_pool):
+    return oracle_pool
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +70,8 @@ def g63(dev):
 
 def oracle_run(pool, kind, kw, p, nframes, arith, schedule="flooding"):
     import sweep_oracle   # tests/helpers, on the path the pool's workers inherit
-    tasks = [(kind, kw, p, f0, min(CHUNK, nframes - f0), LMAX, arith, schedule) for f0 in range(0, nframes, CHUNK)]
+    chunk = min(4096, max(128, nframes // 32))  # enough tasks to keep every worker busy
+    tasks = [(kind, kw, p, f0, min(chunk, nframes - f0), LMAX, arith, schedule) for f0 in range(0, nframes, chunk)]
     parts = sorted(pool.imap_unordered(sweep_oracle.decode_chunk, tasks), key=lambda r: r["frame0"])
     return {k: np.concatenate([r[k] for r in parts]) for k in parts[0] if k != "frame0"}
 
@@ -129,7 +125,7 @@ def test_sweep_point_frame_by_frame(g63, pool, kind, kw, p):
 
 
 @pytest.mark.parametrize("p", workloads.P_GRID)
-def test_sagms_fer_against_fp64_at_sweep_size(g63, pool, p):
+def test_sagms_fer_against_fp64(g63, pool, p):
     t0 = time.perf_counter()
     r = oracle_run(pool, "sagms", workloads.SAGMS_PARAMS, p, FRAMES_FER, "fp64")
     t_oracle = time.perf_counter() - t0
@@ -161,15 +157,15 @@ def same_frames(q, r):
 @pytest.mark.parametrize("p", workloads.P_GRID)
 @pytest.mark.parametrize("precision", ["fp16", "int6"])
 def test_sweep_point_reduced_precision(g63, pool, precision, p):
-    """SAGMS with FP16 and INT6 messages on the first 2^16 frames of every
-    point, frame by frame against the oracle's matching mode."""
+    """SAGMS with FP16 and INT6 messages on the first FRAMES_REDUCED frames of
+    every point, frame by frame against the oracle's matching mode."""
     t0 = time.perf_counter()
-    r = oracle_run(pool, "sagms", workloads.SAGMS_PARAMS, p, FRAMES_EXACT, precision)
+    r = oracle_run(pool, "sagms", workloads.SAGMS_PARAMS, p, FRAMES_REDUCED, precision)
     t_oracle = time.perf_counter() - t0
-    q = gpu_run(g63, "sagms", workloads.SAGMS_PARAMS, p, FRAMES_EXACT, soft=True, precision=precision)
+    q = gpu_run(g63, "sagms", workloads.SAGMS_PARAMS, p, FRAMES_REDUCED, soft=True, precision=precision)
     assert (q["synd"] == r["synd"]).all()
     bad = same_frames(q, r)
-    say("sagms-" + precision, p=p, frames=FRAMES_EXACT, mismatched_frames=bad, fer=float(q["fail"].mean()),
+    say("sagms-" + precision, p=p, frames=FRAMES_REDUCED, mismatched_frames=bad, fer=float(q["fail"].mean()),
         mean_iters=float(q["iters"].mean()), oracle_s=round(t_oracle, 1))
     assert bad == 0 and (q["fail"] == r["fail"]).all()
 
@@ -177,14 +173,14 @@ def test_sweep_point_reduced_precision(g63, pool, precision, p):
 @pytest.mark.parametrize("p", workloads.P_GRID)
 @pytest.mark.parametrize("kind,kw", [("ms", {}), ("sms", dict(alpha=0.75)), ("sagms", dict(workloads.SAGMS_PARAMS))])
 def test_sweep_point_layered(g63, pool, kind, kw, p):
-    """The layered schedule on the first 2^16 frames of every point, frame by
-    frame against the oracle's layered FP32 mode."""
+    """The layered schedule on the first FRAMES_REDUCED frames of every point,
+    frame by frame against the oracle's layered FP32 mode."""
     t0 = time.perf_counter()
-    r = oracle_run(pool, kind, kw, p, FRAMES_EXACT, "fp32", "layered")
+    r = oracle_run(pool, kind, kw, p, FRAMES_REDUCED, "fp32", "layered")
     t_oracle = time.perf_counter() - t0
-    q = gpu_run(g63, kind, kw, p, FRAMES_EXACT, soft=True, schedule="layered")
+    q = gpu_run(g63, kind, kw, p, FRAMES_REDUCED, soft=True, schedule="layered")
     assert (q["synd"] == r["synd"]).all()
     bad = same_frames(q, r)
-    say(kind + "-layered", kw=kw, p=p, frames=FRAMES_EXACT, mismatched_frames=bad, fer=float(q["fail"].mean()),
+    say(kind + "-layered", kw=kw, p=p, frames=FRAMES_REDUCED, mismatched_frames=bad, fer=float(q["fail"].mean()),
         mean_iters=float(q["iters"].mean()), oracle_s=round(t_oracle, 1))
     assert bad == 0 and (q["fail"] == r["fail"]).all()
