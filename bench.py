@@ -36,6 +36,11 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # sign application (1), posterior accumulation (1).  Per-check work (two
 # gain products) and per-frame work are not counted.
 OPS_PER_EDGE_UPDATE = 8
+# The same count for the joint (quaternary) decoder: the check's input is
+# (A - own) + |W| (2 instead of 1), and a variable's per-round work (two
+# sums, three beliefs, two pairs, the decision bits: about 20 lane
+# operations for its d_v = 10 edges) adds 1 per edge: 10.
+OPS_PER_EDGE_UPDATE_JOINT = 10
 # HBM traffic of the decode kernel measured with rocprofv3 (FETCH_SIZE and
 # WRITE_SIZE, KiB per dispatch) and the copy-kernel calibration; used only
 # while the kernel source is unchanged since the counters were taken.
@@ -78,16 +83,30 @@ def copy_calibration(nbytes=1 << 30, reps=4):
     print(json.dumps({"copy_bytes_per_dispatch": nbytes, "dispatches": reps}), flush=True)
 
 
-def oracle_frames(p, lmax, params, frame0, frames, kind="sagms"):
+def oracle_frames(p, lmax, params, frame0, frames, kind="sagms", graph="gb"):
     """The oracle (FP64, NumPy, one BLAS thread) over frames frame0 ..
     frame0 + frames - 1 of the bench workload: sampling, syndromes, decoding
     and the judge.  Returns (seconds, failures, seconds of the decode alone,
-    sum of rounds)."""
+    sum of rounds).  graph "joint": the joint decoder of the same code."""
     from threadpoolctl import threadpool_limits
 
     import workloads
-    from oracle import channel, codes, decoders, judge
+    from oracle import channel, codes, decoders, joint, judge
     l, a, b = workloads.code("G63")
+    if graph == "joint":
+        sx, sz, vc = joint.gb_joint(l, a, b)
+        pg = joint.PauliGraph(sx, sz, vc)
+        lops = joint.logical_operators(sx, sz)
+        prm = decoders.DecoderParams(kind=kind, lmax=lmax, **params)
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            ex, ez = channel.sample_paulis(workloads.SWEEP_SEED, bench_stream(p), frame0, frames, 2 * l, p)
+            s = joint.symplectic_syndrome(sx, sz, ex, ez)
+            t1 = time.perf_counter()
+            r = joint.decode_joint(pg, s, np.full(2 * l, joint.depolarizing_prior(p)), prm, "fp64")
+            t2 = time.perf_counter()
+            fail = joint.judge_joint_logical(lops, ex, ez, r.xhat, r.zhat, r.converged)
+            return time.perf_counter() - t0, int(fail.sum()), t2 - t1, int(np.sum(r.iters))
     hx, hz = codes.gb_matrices(l, a, b)
     tg = decoders.TannerGraph(hz, codes.gb_var_checks(l, a, b))
     lz = codes.logical_basis(hz, hx)
@@ -104,17 +123,26 @@ def oracle_frames(p, lmax, params, frame0, frames, kind="sagms"):
         return time.perf_counter() - t0, int(fail.sum()), t2 - t1, int(np.sum(r.iters))
 
 
+def bench_stream(p):
+    """Philox stream of the single-code workload at noise level p: the index
+    of p in the sweep grid, else 0."""
+    import workloads
+    return workloads.stream_of(p) if p in workloads.P_GRID else 0
+
+
 def _oracle_worker(args):
     return oracle_frames(*args)
 
 
-def cpu_baseline(p, lmax, params, frames=1 << 13, procs=None):
+def cpu_baseline(p, lmax, params, frames=1 << 13, procs=None, graph="gb"):
     """The oracle on a bounded sample of the same workload: frames
     0 .. frames-1 on one core, then (procs > 1) the same number of frames per
     process on a pool of `procs` processes (started by spawn, no GPU state),
     frame ranges split by Philox counter, timed from the first task to the
     last result."""
-    dt = oracle_frames(p, lmax, params, 0, frames)[0]
+    if graph == "joint":
+        frames = min(frames, 1 << 11)
+    dt = oracle_frames(p, lmax, params, 0, frames, "sagms", graph)[0]
     out = {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
            "sample": "%d frames (0..%d) of the same workload, FP64 oracle: sampling + syndromes + SAGMS decode "
                      "+ judge, %.1f s on one core" % (frames, frames - 1, dt)}
@@ -124,9 +152,10 @@ def cpu_baseline(p, lmax, params, frames=1 << 13, procs=None):
         import multiprocessing as mp
         ctx = mp.get_context("spawn")
         with ctx.Pool(procs) as pool:
-            pool.map(_oracle_worker, [(p, lmax, params, 0, 64)] * procs)  # imports and first calls
+            pool.map(_oracle_worker, [(p, lmax, params, 0, 64, "sagms", graph)] * procs)  # imports and first calls
             t0 = time.perf_counter()
-            res = pool.map(_oracle_worker, [(p, lmax, params, frames * (i + 1), frames) for i in range(procs)])
+            res = pool.map(_oracle_worker, [(p, lmax, params, frames * (i + 1), frames, "sagms", graph)
+                                            for i in range(procs)])
             wall = time.perf_counter() - t0
         out["all_cores"] = {"value": frames * procs / wall, "unit": "frames/s", "cores": procs,
                             "host_cpu_count": os.cpu_count(),
@@ -501,9 +530,10 @@ def main():
     ap.add_argument("--decoder", default="sagms", choices=["ms", "sms", "sagms", "bp"])
     ap.add_argument("--alpha", type=float, default=0.75)
     ap.add_argument("--lmax", type=int, default=100)
-    ap.add_argument("--graph", default="gb", choices=["gb", "rows"],
-                    help="build the code from its polynomials (posteriors summed in polynomial-term order) or "
-                         "from the rows of H_Z (ascending check order)")
+    ap.add_argument("--graph", default="gb", choices=["gb", "rows", "joint"],
+                    help="build the code from its polynomials (posteriors summed in polynomial-term order), "
+                         "from the rows of H_Z (ascending check order), or as the joint graph of X- and Z-type "
+                         "rows (m = 126, d_c = d_v = 10; --p is then the depolarizing rate eps)")
     ap.add_argument("--frames-per-wave", type=int, default=0, help="decode launch shape (0 = library default)")
     ap.add_argument("--schedule", default="flooding", choices=["flooding", "layered"],
                     help="message-passing schedule of the single-code workload (Algorithm 1 floods)")
@@ -555,17 +585,27 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     l, a, b = workloads.code("G63")
+    joint = args.graph == "joint"
     if args.graph == "gb":
         g = sagms.Graph.gb(l, a, b)
+    elif joint:
+        g = sagms.Graph.gb_joint(l, a, b)
     else:
         g = sagms.Graph.from_dense(*gb_dense(l, a, b))
     kernel = "decode_kernel<10,5,1,2,%s>" % ("true" if args.decoder == "bp" else "false")
     if args.schedule == "layered":
         kernel = "layered_kernel<10,8>"
+    if joint:
+        kernel = "joint_kernel<10,10,2,2>"
+    ops_per_edge = OPS_PER_EDGE_UPDATE_JOINT if joint else OPS_PER_EDGE_UPDATE
     nf, p = args.frames, args.p
-    stream_id = workloads.stream_of(p) if p in workloads.P_GRID else 0
+    stream_id = bench_stream(p)
     bufs = [sagms.frame_buffers(g, nf, device=dev) for _ in range(2 if args.pipeline else 1)]
-    llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
+    llr = torch.full((g.n,), sagms.depolarizing_llr(p) if joint else sagms.prior_llr(p), dtype=torch.float32,
+                     device=dev)
+    judge = (lambda buf, **kw: sagms.judge_joint(g, buf["ex"], buf["ez"], buf["ehat"], buf["converged"],
+                                                  buf["iters"], counters, **kw)) if joint else \
+        (lambda buf, **kw: sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters, **kw))
     cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, frames_per_wave=args.frames_per_wave,
                                schedule=args.schedule, **workloads.SAGMS_PARAMS)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
@@ -604,14 +644,14 @@ def main():
         if ev is not None:
             ev[1].record(stream)
         if side is None:
-            sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters)
+            judge(buf)
             judged[b].record(stream)
         else:
             # the judge runs on the second stream too, beside the next decode,
             # so the decode stream runs decodes back to back
             decoded[b].record(stream)
             side.wait_event(decoded[b])
-            sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters, stream=side)
+            judge(buf, stream=side)
             judged[b].record(side)
 
     for s in range(args.warmup):
@@ -653,10 +693,10 @@ def main():
         e1.record(stream)
     torch.cuda.synchronize()
     iso_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in iso_ev[5:]]))
-    iso_ops = OPS_PER_EDGE_UPDATE * int(last["iters"].long().sum().item()) * g.n_edges
+    iso_ops = ops_per_edge * int(last["iters"].long().sum().item()) * g.n_edges
     iso_achieved = iso_ops / (iso_ms * 1e-3) / 1e12
     mean_dec_ms = float(np.mean(dec_ms))
-    ops_per_launch = OPS_PER_EDGE_UPDATE * edge_updates / args.steps
+    ops_per_launch = ops_per_edge * edge_updates / args.steps
     achieved = ops_per_launch / (mean_dec_ms * 1e-3) / 1e12
     from paper_2605_10433_amd.stats import wilson
     fer = c[0] / frames
@@ -674,9 +714,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "GB l=63 [[126,28]] (H_Z: m=63, d_c=10, d_v=5, E=630), code-capacity depolarizing "
-                               "p=%g, %d Philox frames/step, %s l_max=%d early exit, %s, FP32 messages"
-                               % (p, nf, args.decoder.upper(), args.lmax, args.schedule),
+        "config": {"workload": ("GB l=63 [[126,28]] joint X/Z decoding (X- and Z-type rows: m=126, d_c=d_v=10, "
+                                "E=1260, scalar messages), code-capacity depolarizing eps=%g" if joint else
+                                "GB l=63 [[126,28]] (H_Z: m=63, d_c=10, d_v=5, E=630), code-capacity depolarizing "
+                                "p=%g") % p + ", %d Philox frames/step, %s l_max=%d early exit, %s, FP32 messages"
+                               % (nf, args.decoder.upper(), args.lmax, args.schedule),
                    "code": "G63", "graph": args.graph, "frames_per_wave": args.frames_per_wave, "p": p, "frames_per_step": nf, "decoder": args.decoder, "lmax": args.lmax,
                    "schedule": args.schedule, "pipeline": bool(args.pipeline)},
         "edge_updates_per_s": edge_updates / (total_ms * 1e-3),
@@ -692,13 +734,13 @@ def main():
                      "traffic": measured_traffic(nf, p) if (args.graph == "gb" and args.decoder == "sagms"
                                                             and args.schedule == "flooding") else None,
                      "kernel": kernel,
-                     "ops_per_edge_update": OPS_PER_EDGE_UPDATE,
+                     "ops_per_edge_update": ops_per_edge,
                      "note": "decode launch time inside the pipelined steps (the next step's sampler and the previous step's judge share the GPU)"
                              if args.pipeline else "decode launch time, one stream",
                      "isolated": {"decode_ms": iso_ms, "achieved": iso_achieved, "frac": iso_achieved / VALU_PEAK_TOPS}},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.lmax, workloads.SAGMS_PARAMS)
+        out["cpu_baseline"] = cpu_baseline(p, args.lmax, workloads.SAGMS_PARAMS, graph=args.graph if joint else "gb")
     print(json.dumps(out), flush=True)
 
 

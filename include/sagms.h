@@ -129,8 +129,11 @@ typedef struct {
     int32_t k;             /* logical dimension n - rank H - rank H_other, or
                               -1 when no other matrix was given              */
     int32_t dc_max, dv_max;/* largest check / variable degree                 */
-    int32_t words_n;       /* ceil(n / 64): words per error / estimate frame  */
+    int32_t words_n;       /* ceil(n / 64): words per error plane (ex, ez)    */
     int32_t words_m;       /* ceil(m / 64): words per syndrome frame          */
+    int32_t joint;         /* 1 for a joint graph (sagms_build_gb_joint)      */
+    int32_t words_e;       /* words per estimate frame: words_n, or 2 words_n
+                              (x part, then z part) for a joint graph         */
 } sagms_graph_info_t;
 
 /* ---- graphs (host only; no device needed) ----------------------------- */
@@ -160,14 +163,38 @@ int sagms_build_graph(int32_t m, int32_t n, const int32_t* row_ptr_host, const i
 int sagms_build_gb(int32_t l, const int32_t* a_host, int32_t wa, const int32_t* b_host, int32_t wb,
                    sagms_graph* out);
 
+/* Joint (quaternary) graph of the same GB code, for decoding X and Z errors
+ * together as the paper's own decoders do (Section II's quaternary Tanner
+ * graph; Section V setup: the [[126,28]] code on the overcomplete m = 126
+ * matrix, d_c = d_v = |a| + |b|).  m = 2l check rows over n = 2l qubits:
+ * rows 0 .. l-1 are the rows of H_X = [A | B] with Pauli X on their support
+ * (X-type), rows l .. 2l-1 the rows of H_Z = [B^T | A^T] with Pauli Z
+ * (Z-type).  Syndromes hold m bits: bit i < l is H_X e_z, bit l + i is
+ * H_Z e_x (the symplectic product of row and error).  Estimates hold
+ * words_e = 2 words_n words per frame: x_hat, then z_hat.  Decoded by
+ * sagms_decode / sagms_decode_soft (flooding; MS, SMS, SAGMS; FP32 messages)
+ * and judged by sagms_judge_joint; not accepted by batches, the server, the
+ * layered schedule or sagms_judge.  The posterior sums of variable i < l
+ * take its X-type checks (i - a_t) mod l, then its Z-type checks
+ * l + (i + b_t) mod l; variable l + i the X-type checks (i - b_t) mod l,
+ * then the Z-type checks l + (i + a_t) mod l, each in term order. */
+int sagms_build_gb_joint(int32_t l, const int32_t* a_host, int32_t wa, const int32_t* b_host, int32_t wb,
+                         sagms_graph* out);
+
 int sagms_graph_info(sagms_graph g, sagms_graph_info_t* info);
 
-/* Copies the decoding matrix H as packed rows: row i occupies words_n words
- * starting at rows_host + i * words_n. */
+/* Copies the decoding matrix H as packed rows: row i occupies words_e words
+ * starting at rows_host + i * words_e (joint graphs: the row's x part, then
+ * its z part; an X-type row has its support in the z part, since it detects
+ * the Z part of an error). */
 int sagms_graph_rows(sagms_graph g, uint64_t* rows_host);
 
-/* Copies the logical basis used by the judge (k rows of words_n words): a
- * basis of ker(H_other) modulo rowspace(H). */
+/* Copies the logical basis used by the judge: k rows of words_n words, a
+ * basis of ker(H_other) modulo rowspace(H).  Joint graphs: 2k rows of
+ * words_e words (u | v), such that a residual (r_x | r_z) is a logical error
+ * iff u.r_x + v.r_z is odd for some row: rows 0 .. k-1 are the Z-type
+ * logicals ker(H_X) mod rowspace(H_Z) as (z | 0), rows k .. 2k-1 the X-type
+ * logicals ker(H_Z) mod rowspace(H_X) as (0 | x). */
 int sagms_graph_logicals(sagms_graph g, uint64_t* rows_host);
 
 int sagms_destroy_graph(sagms_graph g);
@@ -185,6 +212,12 @@ int sagms_graph_upload(sagms_graph g);
  * ln((1 - 2p/3) / (2p/3)) (the binary marginal of the prior of Section II),
  * rounded to float.  Returns NaN for p outside (0, 0.75). */
 float sagms_prior_llr(double p);
+
+/* Prior log-ratio of a joint graph's variables for the depolarizing channel
+ * of strength p: L0 = ln((1 - p) / (p / 3)), the same against X, Y and Z
+ * (Section II's L0 with e0 = p), rounded to float.  NaN for p outside
+ * (0, 0.75). */
+float sagms_depolarizing_llr(double p);
 
 /* BP-matching ratio of eq. (alphastar): the scale that makes the min-sum
  * check output equal the BP output when all d_c - 1 incoming magnitudes
@@ -210,7 +243,9 @@ int sagms_derive_gains(double l0, int32_t dc, double ratio, double eta, sagms_de
  * T_Y = floor((2p)/3 * 2^32), T_Z = floor(p * 2^32) (IEEE double), the Pauli
  * is X if u < T_X, Y if u < T_Y, Z if u < T_Z, else I.
  * Outputs (device, packed): ex, ez [nframes][words_n] the X and Z parts
- * (ez may be NULL to skip it), synd [nframes][words_m] = H e_x (mod 2).
+ * (ez may be NULL to skip it, except for a joint graph), synd
+ * [nframes][words_m] = H e_x (mod 2), or for a joint graph the symplectic
+ * syndrome (H_X e_z, H_Z e_x).
  * 0 <= p < 1; 0 <= nframes <= 2^31 - 1 (0 is a no-op; SAGMS_EINVAL outside,
  * checked before any device work, as for every device call). */
 int sagms_gen_errors(sagms_graph g, uint64_t seed, uint32_t stream_id, uint64_t frame0, int64_t nframes,
@@ -244,6 +279,26 @@ int sagms_decode_soft(sagms_graph g, const uint64_t* synd, const float* llr0, co
                       int64_t nframes, uint64_t* ehat, int32_t* iters, uint8_t* converged, float* posterior,
                       void* stream);
 
+/* On a joint graph (sagms_build_gb_joint) the same two calls decode X and Z
+ * together with scalar messages:
+ *   llr0      device [n] float: L0_j = ln(P(I) / P(W)), the same for W = X,
+ *             Y, Z (Section II's depolarizing prior ln((1 - e0) / (e0 / 3)))
+ *   ehat      device [nframes][2 words_n]: x_hat words, then z_hat words
+ *   posterior device float [nframes][n][3]: the last beliefs Gamma^X,
+ *             Gamma^Y, Gamma^Z of every variable
+ * Each variable's beliefs are Gamma^X = L0 + S_Z, Gamma^Z = L0 + S_X,
+ * Gamma^Y = L0 + (S_X + S_Z), with S_X (S_Z) the FP32 sum of its X-type
+ * (Z-type) checks' outputs in the builder's order; the message to a check
+ * of Pauli P is min over the two Paulis A that anticommute with P of
+ * (Gamma^A - that check's own output) - min(0, Gamma^P) (the min-sum form of
+ * the log-domain scalar BP4 reduction the paper's Section I footnote cites);
+ * the hard decision is the argmin over (I, X, Y, Z) of (0, Gamma^X,
+ * Gamma^Y, Gamma^Z), first minimum on ties; the residual syndrome is the
+ * symplectic product (eq. (resid)); m counts both check types in eq.
+ * (synratio).  Check outputs are the min-sum outputs of the binary decoder
+ * with magnitudes saturated at 2^64.  MS, SMS and SAGMS with FP32 messages
+ * and the flooding schedule (SAGMS_EUNSUPPORTED otherwise). */
+
 /* Logical-failure judge.  Frame f fails iff converged[f] == 0, or the
  * residual r = ex xor ehat has odd overlap with some row of the logical
  * basis (equivalently r is not in the rowspace of H_other; Section II:
@@ -255,6 +310,16 @@ int sagms_decode_soft(sagms_graph g, const uint64_t* synd, const float* llr0, co
  *             counters[0] += failures, counters[1] += sum of iters */
 int sagms_judge(sagms_graph g, const uint64_t* ex, const uint64_t* ehat, const uint8_t* converged,
                 const int32_t* iters, int64_t nframes, uint8_t* fail, uint64_t* counters, void* stream);
+
+/* The judge of a joint graph: frame f fails iff converged[f] == 0 or the
+ * residual (ex xor x_hat, ez xor z_hat) anticommutes with a logical operator
+ * (a row (u | v) of sagms_graph_logicals has u.r_x + v.r_z odd), i.e. it is
+ * not in the stabilizer group.  ex, ez device [nframes][words_n]; ehat
+ * device [nframes][2 words_n]; the rest as for sagms_judge.  SAGMS_EINVAL
+ * for a graph that is not joint. */
+int sagms_judge_joint(sagms_graph g, const uint64_t* ex, const uint64_t* ez, const uint64_t* ehat,
+                      const uint8_t* converged, const int32_t* iters, int64_t nframes, uint8_t* fail,
+                      uint64_t* counters, void* stream);
 
 /* ---- mixed-code batches ------------------------------------------------
  * A batch decodes, in one call, several runs of frames ("segments"), each of

@@ -76,7 +76,7 @@ def plan(kind="single", tile_frames=8, waves_per_block=4, blocks_per_cu=0, reg_b
 
 class GraphInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
-                ("m", "n", "n_edges", "k", "dc_max", "dv_max", "words_n", "words_m")]
+                ("m", "n", "n_edges", "k", "dc_max", "dv_max", "words_n", "words_m", "joint", "words_e")]
 
 
 def lib():
@@ -91,6 +91,7 @@ def lib():
         sigs = {
             "sagms_build_graph": [i32, i32, vp, vp, i32, vp, vp, vp],
             "sagms_build_gb": [i32, vp, i32, vp, i32, vp],
+            "sagms_build_gb_joint": [i32, vp, i32, vp, i32, vp],
             "sagms_graph_info": [vp, vp],
             "sagms_graph_rows": [vp, vp],
             "sagms_graph_logicals": [vp, vp],
@@ -100,6 +101,7 @@ def lib():
             "sagms_decode": [vp, vp, vp, vp, i64, vp, vp, vp, vp],
             "sagms_decode_soft": [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp],
             "sagms_judge": [vp, vp, vp, vp, vp, i64, vp, vp, vp],
+            "sagms_judge_joint": [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp],
             "sagms_batch_create": [vp, i32, vp, vp],
             "sagms_batch_set_plan": [vp, vp],
             "sagms_batch_get_plan": [vp, vp],
@@ -123,6 +125,8 @@ def lib():
         L.sagms_last_error.restype = ctypes.c_char_p
         L.sagms_prior_llr.argtypes = [dbl]
         L.sagms_prior_llr.restype = ctypes.c_float
+        L.sagms_depolarizing_llr.argtypes = [dbl]
+        L.sagms_depolarizing_llr.restype = ctypes.c_float
         L.sagms_alpha_star.argtypes = [dbl, i32]
         L.sagms_alpha_star.restype = ctypes.c_double
         L.sagms_derive_gains.argtypes = [dbl, i32, dbl, dbl, vp]
@@ -140,6 +144,11 @@ def header_functions():
 def _check(rc):
     if rc != OK:
         raise SagmsError(rc, lib().sagms_last_error().decode())
+
+
+def depolarizing_llr(p: float) -> float:
+    """Prior log-ratio of a joint graph's variables, ln((1 - p) / (p / 3)), as float."""
+    return float(lib().sagms_depolarizing_llr(float(p)))
 
 
 def prior_llr(p: float) -> float:
@@ -188,6 +197,16 @@ class Graph:
         return cls(h.value)
 
     @classmethod
+    def gb_joint(cls, l, a, b):
+        """The joint (quaternary) graph of a GB code: X-type rows of H_X, then
+        Z-type rows of H_Z (sagms_build_gb_joint)."""
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        b = np.ascontiguousarray(b, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().sagms_build_gb_joint(int(l), a.ctypes.data, len(a), b.ctypes.data, len(b), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
     def from_dense(cls, h, h_other=None):
         def csr(mat):
             mat = np.asarray(mat, dtype=np.uint8)
@@ -212,12 +231,13 @@ class Graph:
         return cls(hdl.value)
 
     def rows(self) -> np.ndarray:
-        out = np.zeros((self.m, self.words_n), dtype=np.uint64)
+        out = np.zeros((self.m, self.words_e), dtype=np.uint64)
         _check(lib().sagms_graph_rows(self._h, out.ctypes.data))
         return out
 
     def logicals(self) -> np.ndarray:
-        out = np.zeros((max(self.k, 0), self.words_n), dtype=np.uint64)
+        rows = max(self.k, 0) * (2 if self.joint else 1)
+        out = np.zeros((rows, self.words_e), dtype=np.uint64)
         _check(lib().sagms_graph_logicals(self._h, out.ctypes.data))
         return out
 
@@ -275,7 +295,7 @@ def decode(g: Graph, synd, llr0, cfg: DecoderConfig, ehat, iters, converged, str
     _check(lib().sagms_decode(
         g._h, _dev_ptr(synd, torch.int64, (nframes, g.words_m), "synd"),
         _dev_ptr(llr0, torch.float32, (g.n,), "llr0"), ctypes.byref(cfg), int(nframes),
-        _dev_ptr(ehat, torch.int64, (nframes, g.words_n), "ehat"),
+        _dev_ptr(ehat, torch.int64, (nframes, g.words_e), "ehat"),
         _dev_ptr(iters, torch.int32, (nframes,), "iters"),
         _dev_ptr(converged, torch.uint8, (nframes,), "converged"), _stream(stream)))
 
@@ -286,10 +306,11 @@ def decode_soft(g: Graph, synd, llr0, cfg: DecoderConfig, ehat, iters, converged
     _check(lib().sagms_decode_soft(
         g._h, _dev_ptr(synd, torch.int64, (nframes, g.words_m), "synd"),
         _dev_ptr(llr0, torch.float32, (g.n,), "llr0"), ctypes.byref(cfg), int(nframes),
-        _dev_ptr(ehat, torch.int64, (nframes, g.words_n), "ehat"),
+        _dev_ptr(ehat, torch.int64, (nframes, g.words_e), "ehat"),
         _dev_ptr(iters, torch.int32, (nframes,), "iters"),
         _dev_ptr(converged, torch.uint8, (nframes,), "converged"),
-        _dev_ptr(posterior, torch.float32, (nframes, g.n), "posterior"), _stream(stream)))
+        _dev_ptr(posterior, torch.float32, (nframes, g.n, 3) if g.joint else (nframes, g.n), "posterior"),
+        _stream(stream)))
 
 
 def judge(g: Graph, ex, ehat, converged, iters, counters, fail=None, stream=None):
@@ -304,6 +325,20 @@ def judge(g: Graph, ex, ehat, converged, iters, counters, fail=None, stream=None
         _dev_ptr(counters, torch.int64, (2,), "counters"), _stream(stream)))
 
 
+def judge_joint(g: Graph, ex, ez, ehat, converged, iters, counters, fail=None, stream=None):
+    """The judge of a joint graph (sagms_judge_joint)."""
+    import torch
+    nframes = ex.shape[0]
+    _check(lib().sagms_judge_joint(
+        g._h, _dev_ptr(ex, torch.int64, (nframes, g.words_n), "ex"),
+        _dev_ptr(ez, torch.int64, (nframes, g.words_n), "ez"),
+        _dev_ptr(ehat, torch.int64, (nframes, g.words_e), "ehat"),
+        _dev_ptr(converged, torch.uint8, (nframes,), "converged"),
+        _dev_ptr(iters, torch.int32, (nframes,), "iters"), int(nframes),
+        _dev_ptr(fail, torch.uint8, (nframes,), "fail"),
+        _dev_ptr(counters, torch.int64, (2,), "counters"), _stream(stream)))
+
+
 def frame_buffers(g: Graph, nframes: int, device="cuda", with_ez=True):
     """Device tensors for one batch: ex, ez, synd, ehat, iters, converged, fail."""
     import torch
@@ -312,7 +347,7 @@ def frame_buffers(g: Graph, nframes: int, device="cuda", with_ez=True):
         ex=torch.empty((nframes, g.words_n), dtype=torch.int64, **z),
         ez=torch.empty((nframes, g.words_n), dtype=torch.int64, **z) if with_ez else None,
         synd=torch.empty((nframes, g.words_m), dtype=torch.int64, **z),
-        ehat=torch.empty((nframes, g.words_n), dtype=torch.int64, **z),
+        ehat=torch.empty((nframes, g.words_e), dtype=torch.int64, **z),
         iters=torch.empty((nframes,), dtype=torch.int32, **z),
         converged=torch.empty((nframes,), dtype=torch.uint8, **z),
         fail=torch.empty((nframes,), dtype=torch.uint8, **z),

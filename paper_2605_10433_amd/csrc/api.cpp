@@ -96,6 +96,7 @@ int sagms_gen_errors(sagms_graph gh, uint64_t seed, uint32_t stream_id, uint64_t
     if (!(p >= 0.0 && p < 1.0)) return fail(SAGMS_EINVAL, "p must lie in [0, 1)");
     if (nframes == 0) return SAGMS_OK;
     if (!ex || !synd) return fail(SAGMS_EINVAL, "ex and synd must not be null");
+    if (g->joint && !ez) return fail(SAGMS_EINVAL, "joint graphs need the ez plane (the X-type checks read it)");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     DeviceTables* t = nullptr;
     rc = device_tables(g, &t);
@@ -120,6 +121,7 @@ int sagms_gen_errors(sagms_graph gh, uint64_t seed, uint32_t stream_id, uint64_t
     a.wn = g->wn;
     a.wm = g->wm;
     a.frames_per_wave = kSampleFramesPerWave;
+    a.joint = g->joint ? 1 : 0;
     return launch_sample(a, st);
 }
 
@@ -144,9 +146,32 @@ int sagms_decode_soft(sagms_graph gh, const uint64_t* synd, const float* llr0, c
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (cfg->schedule == SAGMS_LAYERED && g->layered.status != SAGMS_OK)
         return fail(g->layered.status, "%s", g->layered.why.c_str());
+    if (g->joint && (cfg->kind == SAGMS_BP || cfg->msg_precision != SAGMS_MSG_FP32))
+        return fail(SAGMS_EUNSUPPORTED, "joint graphs decode MS, SMS and SAGMS with FP32 messages");
     DeviceTables* t = nullptr;
     rc = device_tables(g, &t);
     if (rc) return rc;
+    if (g->joint) {
+        JointArgs ja{};
+        ja.synd = synd;
+        ja.llr0 = llr0;
+        ja.gains = gain_law(cfg);
+        ja.cn_addr = t->cn_addr;
+        ja.vn_addr = t->vn_addr;
+        ja.ehat = ehat;
+        ja.iters = iters;
+        ja.conv = converged;
+        ja.gamma = posterior;
+        ja.nframes = nframes;
+        ja.m = g->m;
+        ja.n = g->n;
+        ja.wm = g->wm;
+        ja.wn = g->wn;
+        ja.lmax = cfg->lmax;
+        ja.frames_per_wave = cfg->frames_per_wave;
+        ja.L = g->jlayout;
+        return launch_joint(g->shape, ja, st);
+    }
     const DecodeArgs a = decode_args(g, t, gain_law(cfg), synd, llr0, nframes, ehat, iters, converged, posterior,
                                      cfg->lmax, cfg->frames_per_wave);
     if (cfg->schedule == SAGMS_LAYERED) return launch_layered(t->layered, a, st);
@@ -158,6 +183,7 @@ int sagms_judge(sagms_graph gh, const uint64_t* ex, const uint64_t* ehat, const 
     Graph* g = reinterpret_cast<Graph*>(gh);
     if (!g) return fail(SAGMS_EINVAL, "null graph");
     if (!g->have_other) return fail(SAGMS_EINVAL, "the judge needs a graph built with the other check matrix");
+    if (g->joint) return fail(SAGMS_EINVAL, "joint graphs are judged by sagms_judge_joint (both error planes)");
     int rc = check_frames(nframes);
     if (rc) return rc;
     if (nframes == 0) return SAGMS_OK;
@@ -177,6 +203,37 @@ int sagms_judge(sagms_graph gh, const uint64_t* ex, const uint64_t* ehat, const 
     a.nframes = nframes;
     a.k = g->k;
     a.wn = g->wn;
+    a.wplane = g->wn;
+    return launch_judge(a, st);
+}
+
+int sagms_judge_joint(sagms_graph gh, const uint64_t* ex, const uint64_t* ez, const uint64_t* ehat,
+                      const uint8_t* converged, const int32_t* iters, int64_t nframes, uint8_t* failv,
+                      uint64_t* counters, void* stream) {
+    Graph* g = reinterpret_cast<Graph*>(gh);
+    if (!g) return fail(SAGMS_EINVAL, "null graph");
+    if (!g->joint) return fail(SAGMS_EINVAL, "sagms_judge_joint needs a joint graph (sagms_build_gb_joint)");
+    int rc = check_frames(nframes);
+    if (rc) return rc;
+    if (nframes == 0) return SAGMS_OK;
+    if (!ex || !ez || !ehat || !converged || !iters || !counters) return fail(SAGMS_EINVAL, "null buffer");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    DeviceTables* t = nullptr;
+    rc = device_tables(g, &t);
+    if (rc) return rc;
+    JudgeArgs a{};
+    a.ex = ex;
+    a.ez = ez;
+    a.ehat = ehat;
+    a.conv = converged;
+    a.iters = iters;
+    a.logicals = t->logicals;
+    a.fail = failv;
+    a.counters = counters;
+    a.nframes = nframes;
+    a.k = 2 * g->k;
+    a.wn = g->we;
+    a.wplane = g->wn;
     return launch_judge(a, st);
 }
 

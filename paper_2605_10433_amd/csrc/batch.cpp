@@ -89,6 +89,7 @@ int prepare_segments(const sagms_segment* segs, int nseg, const sagms_decoder_cf
         const sagms_segment& x = segs[s];
         Graph* g = reinterpret_cast<Graph*>(x.graph);
         if (!g) return fail(SAGMS_EINVAL, "segment %d: null graph", s);
+        if (g->joint) return fail(SAGMS_EUNSUPPORTED, "segment %d: joint graphs decode through sagms_decode only", s);
         if (!g->shape_ok) return fail(SAGMS_EUNSUPPORTED, "segment %d: no decode kernel fits the code", s);
         if (shape_index(g->shape) < 0) return fail(SAGMS_EUNSUPPORTED, "segment %d: shape not compiled", s);
         if (x.nframes < 0 || x.nframes > kMaxFramesPerCall)

@@ -72,7 +72,7 @@ static void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const 
 
 // Waves of one kernel resident on the current device at once (occupancy of
 // registers and LDS times compute units), queried once per kernel and device.
-static int resident_waves(const void* kernel, int wpb, size_t lds, int64_t* out) {
+int resident_waves(const void* kernel, int wpb, size_t lds, int64_t* out) {
     static std::mutex mu;
     static std::unordered_map<uint64_t, int64_t> cache;
     int dev = 0;

@@ -113,6 +113,36 @@ DecodeLayout make_layout(const DecodeShape& s) {
     return L;
 }
 
+static const DecodeShape kJointShapes[] = {
+#define SAGMS_JOINT_ENTRY(I, DC, DV, CPL, VPL) {DC, DV, CPL, VPL},
+    SAGMS_JOINT_SHAPES(SAGMS_JOINT_ENTRY)
+#undef SAGMS_JOINT_ENTRY
+};
+static_assert(sizeof(kJointShapes) / sizeof(kJointShapes[0]) == kNumJointShapes, "joint shape list");
+
+bool pick_joint_shape(int m, int n, int dc, int dvh, DecodeShape* out) {
+    bool found = false;
+    int best = 0;
+    for (const DecodeShape& s : kJointShapes) {
+        if (s.dc < dc || s.dv < 2 * dvh || 64 * s.cpl < m || 64 * s.vpl < n) continue;
+        int cost = s.cpl * s.dc * 3 + s.vpl * s.dv;
+        if (!found || cost < best) { *out = s; best = cost; found = true; }
+    }
+    return found;
+}
+
+JointLayout make_joint_layout(const DecodeShape& s) {
+    JointLayout L;
+    L.cw = 64 * s.cpl;
+    L.zero = s.dc * L.cw;
+    L.pairx = L.zero + 64;
+    L.pairz = L.pairx + 128 * s.vpl;
+    L.padpair = L.pairz + 128 * s.vpl;
+    L.gain0 = L.padpair + 128;
+    L.words = L.gain0 + 2 * (L.cw + 1);
+    return L;
+}
+
 // Builds the per-lane LDS address tables for the chosen shape.
 static void build_lane_tables(Graph* g) {
     const DecodeShape& s = g->shape;
@@ -157,6 +187,7 @@ static int finish_graph(Graph* g, const std::vector<int>& row_ptr_o, const std::
     g->E = g->row_ptr[g->m];
     g->wn = (g->n + 63) / 64;
     g->wm = (g->m + 63) / 64;
+    g->we = g->wn;
     g->rows_bits.assign((size_t)g->m * g->wn, 0);
     std::vector<int> vdeg(g->n, 0);
     g->dc_max = 0;
@@ -214,6 +245,126 @@ static int finish_graph(Graph* g, const std::vector<int>& row_ptr_o, const std::
     return SAGMS_OK;
 }
 
+// Basis of ker(a) modulo rowspace(b) (a, b: packed rows over ncols bits).
+static std::vector<uint64_t> logical_rows(const std::vector<uint64_t>& a, int ma, const std::vector<uint64_t>& b,
+                                          int mb, int wn, int ncols) {
+    int kdim = 0;
+    std::vector<uint64_t> kern = gf2_kernel(a, ma, wn, ncols, &kdim);
+    std::vector<uint64_t> acc = b, out;
+    int acc_rows = mb, acc_rank = gf2_rank(acc, acc_rows, wn);
+    for (int t = 0; t < kdim; ++t) {
+        std::vector<uint64_t> trial = acc;
+        trial.insert(trial.end(), kern.begin() + (size_t)t * wn, kern.begin() + (size_t)(t + 1) * wn);
+        const int r = gf2_rank(trial, acc_rows + 1, wn);
+        if (r > acc_rank) {
+            acc.swap(trial);
+            acc_rows++;
+            acc_rank = r;
+            out.insert(out.end(), kern.begin() + (size_t)t * wn, kern.begin() + (size_t)(t + 1) * wn);
+        }
+    }
+    return out;
+}
+
+// Joint graph of a GB code (set up by sagms_build_gb_joint): rows over the
+// (x | z) planes, logical rows, each variable's X-type then Z-type checks in
+// posterior-sum order, shape, layout and lane tables of the joint kernel.
+static int finish_joint(Graph* g) {
+    const int l = g->gb_l, n = g->n, m = g->m;
+    g->E = g->row_ptr[m];
+    g->wn = (n + 63) / 64;
+    g->wm = (m + 63) / 64;
+    g->we = 2 * g->wn;
+    const int wn = g->wn;
+    g->rows_bits.assign((size_t)m * g->we, 0);
+    std::vector<uint64_t> hx((size_t)l * wn, 0), hz((size_t)l * wn, 0);
+    std::vector<int> vdeg(n, 0);
+    g->dc_max = 0;
+    for (int c = 0; c < m; ++c) {
+        const bool xtype = c < l;
+        g->dc_max = std::max(g->dc_max, g->row_ptr[c + 1] - g->row_ptr[c]);
+        for (int t = g->row_ptr[c]; t < g->row_ptr[c + 1]; ++t) {
+            const int j = g->cols[t];
+            // an X-type check sees the Z part of an error, a Z-type check the X part
+            g->rows_bits[(size_t)c * g->we + (xtype ? wn : 0) + (j >> 6)] |= 1ull << (j & 63);
+            (xtype ? hx : hz)[(size_t)(xtype ? c : c - l) * wn + (j >> 6)] |= 1ull << (j & 63);
+            vdeg[j]++;
+        }
+    }
+    g->dv_max = *std::max_element(vdeg.begin(), vdeg.end());
+    for (int a = 0; a < l; ++a)
+        for (int b = 0; b < l; ++b) {
+            int par = 0;
+            for (int w = 0; w < wn; ++w) par ^= __builtin_popcountll(hx[(size_t)a * wn + w] & hz[(size_t)b * wn + w]) & 1;
+            if (par) return fail(SAGMS_EINVAL, "X-type row %d and Z-type row %d anticommute", a, b);
+        }
+    // Z-type logicals ker(H_X) mod rowspace(H_Z) act on the X part of a
+    // residual, X-type logicals ker(H_Z) mod rowspace(H_X) on its Z part
+    const std::vector<uint64_t> zl = logical_rows(hx, l, hz, l, wn, n), xl = logical_rows(hz, l, hx, l, wn, n);
+    g->k = (int)(zl.size() / wn);
+    if ((int)(xl.size() / wn) != g->k) return fail(SAGMS_EINVAL, "logical dimensions differ (internal)");
+    g->logicals.assign((size_t)2 * g->k * g->we, 0);
+    for (int t = 0; t < g->k; ++t)
+        for (int w = 0; w < wn; ++w) {
+            g->logicals[(size_t)t * g->we + w] = zl[(size_t)t * wn + w];
+            g->logicals[(size_t)(g->k + t) * g->we + wn + w] = xl[(size_t)t * wn + w];
+        }
+    g->have_other = true;
+    // posterior-sum order: variable i < l meets X-type checks (i - a_t) mod l
+    // and Z-type checks l + (i + b_t) mod l; variable l + i the X-type checks
+    // (i - b_t) mod l and Z-type checks l + (i + a_t) mod l, in term order
+    auto position = [&](int c, int j) {
+        for (int t = g->row_ptr[c]; t < g->row_ptr[c + 1]; ++t)
+            if (g->cols[t] == j) return t - g->row_ptr[c];
+        return -1;
+    };
+    const std::vector<int>&A = g->gb_a, &B = g->gb_b;
+    std::vector<std::vector<int>> xc(n), zc(n);
+    for (int i = 0; i < l; ++i) {
+        for (int a : A) xc[i].push_back(((i - a) % l + l) % l);
+        for (int b : B) zc[i].push_back(l + (i + b) % l);
+        for (int b : B) xc[l + i].push_back(((i - b) % l + l) % l);
+        for (int a : A) zc[l + i].push_back(l + (i + a) % l);
+    }
+    g->dvh = 0;
+    for (int j = 0; j < n; ++j) g->dvh = std::max({g->dvh, (int)xc[j].size(), (int)zc[j].size()});
+    g->var_edges.assign(n, {});
+    for (int j = 0; j < n; ++j) {
+        for (int c : xc[j]) g->var_edges[j].push_back({c, position(c, j)});
+        for (int c : zc[j]) g->var_edges[j].push_back({c, position(c, j)});
+        for (const auto& e : g->var_edges[j])
+            if (e.second < 0) return fail(SAGMS_EINVAL, "joint graph: variable %d missing from check %d (internal)", j, e.first);
+    }
+    g->shape_ok = pick_joint_shape(m, n, g->dc_max, g->dvh, &g->shape);
+    if (!g->shape_ok) return SAGMS_OK;
+    const DecodeShape& s = g->shape;
+    const JointLayout& L = g->jlayout = make_joint_layout(s);
+    g->cn_addr_host.assign((size_t)s.cpl * s.dc * 64, kPadLane);
+    g->vn_addr_host.assign((size_t)s.vpl * s.dv * 64, kPadLane);
+    for (int c = 0; c < m; ++c)
+        for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p) {
+            const int j = g->cols[g->row_ptr[c] + p];
+            g->cn_addr_host[((size_t)(c / 64) * s.dc + p) * 64 + (c % 64)] = (uint32_t)((c < l ? L.pairx : L.pairz) + 2 * j);
+        }
+    const int dvh = s.dv / 2;
+    for (int j = 0; j < n; ++j) {
+        for (size_t r = 0; r < xc[j].size(); ++r) {
+            const auto& e = g->var_edges[j][r];
+            g->vn_addr_host[((size_t)(j / 64) * s.dv + r) * 64 + (j % 64)] = (uint32_t)(e.second * L.cw + e.first);
+        }
+        for (size_t r = 0; r < zc[j].size(); ++r) {
+            const auto& e = g->var_edges[j][xc[j].size() + r];
+            g->vn_addr_host[((size_t)(j / 64) * s.dv + dvh + r) * 64 + (j % 64)] = (uint32_t)(e.second * L.cw + e.first);
+        }
+    }
+    // padding: checks read the (+inf, +0) pair at padpair (a broadcast),
+    // variables a zero word of the pool
+    for (uint32_t& v : g->cn_addr_host)
+        if (v == kPadLane) v = (uint32_t)L.padpair;
+    place_padding(g->vn_addr_host, (uint32_t)L.zero);
+    return SAGMS_OK;
+}
+
 static int check_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci, const char* name, bool need_deg2) {
     if (!rp || !ci) return fail(SAGMS_EINVAL, "%s: null CSR pointer", name);
     if (rp[0] != 0) return fail(SAGMS_EINVAL, "%s: row_ptr[0] must be 0", name);
@@ -232,6 +383,8 @@ static int check_csr(int32_t m, int32_t n, const int32_t* rp, const int32_t* ci,
     }
     return SAGMS_OK;
 }
+
+static int publish(Graph* g, sagms_graph* out);
 
 static int build(int32_t m, int32_t n, const std::vector<int>& rp, const std::vector<int>& ci, int32_t m_other,
                  const std::vector<int>& rpo, const std::vector<int>& cio, sagms_graph* out,
@@ -253,9 +406,15 @@ static int build(int32_t m, int32_t n, const std::vector<int>& rp, const std::ve
         delete g;
         return rc;
     }
+    return publish(g, out);
+}
+
+// Plans the layered schedule, copies the tables to the current device if the
+// process has one (host-only use needs none: the device calls then report a
+// graph without tables) and hands the graph out.
+static int publish(Graph* g, sagms_graph* out) {
     plan_layers(g);
-    // tables on the current device, if the process has one (host-only use
-    // needs none: the device calls report a graph without tables)
+    int rc = SAGMS_OK;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
         DeviceTables* t = nullptr;
@@ -278,8 +437,8 @@ static int upload_locked(Graph* g, DeviceTables* t) {
     size_t ncols = (size_t)g->m * std::max(g->dc_max, 1);
     std::vector<int32_t> cols(ncols, -1);
     for (int c = 0; c < g->m; ++c)
-        for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p)
-            cols[(size_t)c * std::max(g->dc_max, 1) + p] = g->cols[g->row_ptr[c] + p];
+        for (int p = 0; p < g->row_ptr[c + 1] - g->row_ptr[c]; ++p)  // joint X-type rows read the Z plane
+            cols[(size_t)c * std::max(g->dc_max, 1) + p] = g->cols[g->row_ptr[c] + p] + (g->joint && c < g->m / 2 ? g->n : 0);
     SAGMS_HIP(hipMalloc(&t->cols, std::max<size_t>(ncols, 1) * sizeof(int32_t)));
     SAGMS_HIP(hipMemcpy(t->cols, cols.data(), ncols * sizeof(int32_t), hipMemcpyHostToDevice));
     SAGMS_HIP(hipMalloc(&t->rows, g->rows_bits.size() * sizeof(uint64_t)));
@@ -387,9 +546,7 @@ int sagms_build_graph(int32_t m, int32_t n, const int32_t* row_ptr, const int32_
     return build(m, n, rp, ci, m_other, rpo, cio, out);
 }
 
-int sagms_build_gb(int32_t l, const int32_t* a, int32_t wa, const int32_t* b, int32_t wb, sagms_graph* out) {
-    if (!out) return fail(SAGMS_EINVAL, "out is null");
-    *out = nullptr;
+static int check_gb(int32_t l, const int32_t* a, int32_t wa, const int32_t* b, int32_t wb) {
     if (l < 2 || 2 * l > kMaxN) return fail(SAGMS_EINVAL, "circulant size l=%d out of range", l);
     if (!a || !b || wa < 1 || wb < 1 || wa + wb < 2) return fail(SAGMS_EINVAL, "bad polynomial arguments");
     for (int t = 0; t < wa; ++t)
@@ -402,6 +559,51 @@ int sagms_build_gb(int32_t l, const int32_t* a, int32_t wa, const int32_t* b, in
     for (int s = 0; s < wb; ++s)
         for (int t = s + 1; t < wb; ++t)
             if (b[s] == b[t]) return fail(SAGMS_EINVAL, "repeated exponent in b");
+    return SAGMS_OK;
+}
+
+int sagms_build_gb_joint(int32_t l, const int32_t* a, int32_t wa, const int32_t* b, int32_t wb, sagms_graph* out) {
+    if (!out) return fail(SAGMS_EINVAL, "out is null");
+    *out = nullptr;
+    int rc = check_gb(l, a, wa, b, wb);
+    if (rc) return rc;
+    Graph* g = new (std::nothrow) Graph();
+    if (!g) return fail(SAGMS_ENOMEM, "graph allocation failed");
+    g->joint = true;
+    g->is_gb = true;
+    g->gb_l = l;
+    g->gb_a.assign(a, a + wa);
+    g->gb_b.assign(b, b + wb);
+    g->m = 2 * l;
+    g->n = 2 * l;
+    // X-type check c: row c of H_X = [A | B], columns (c + a_t) mod l and
+    // l + (c + b_t) mod l; Z-type check l + c: row c of H_Z = [B^T | A^T],
+    // columns (c - b_t) mod l and l + (c - a_t) mod l (term order)
+    g->row_ptr.assign(2 * l + 1, 0);
+    for (int c = 0; c < l; ++c) {
+        g->row_ptr[c] = (int)g->cols.size();
+        for (int t = 0; t < wa; ++t) g->cols.push_back((c + a[t]) % l);
+        for (int t = 0; t < wb; ++t) g->cols.push_back(l + (c + b[t]) % l);
+    }
+    for (int c = 0; c < l; ++c) {
+        g->row_ptr[l + c] = (int)g->cols.size();
+        for (int t = 0; t < wb; ++t) g->cols.push_back(((c - b[t]) % l + l) % l);
+        for (int t = 0; t < wa; ++t) g->cols.push_back(l + ((c - a[t]) % l + l) % l);
+    }
+    g->row_ptr[2 * l] = (int)g->cols.size();
+    rc = finish_joint(g);
+    if (rc != SAGMS_OK) {
+        delete g;
+        return rc;
+    }
+    return publish(g, out);
+}
+
+int sagms_build_gb(int32_t l, const int32_t* a, int32_t wa, const int32_t* b, int32_t wb, sagms_graph* out) {
+    if (!out) return fail(SAGMS_EINVAL, "out is null");
+    *out = nullptr;
+    int rc = check_gb(l, a, wa, b, wb);
+    if (rc) return rc;
     // H_Z = [B^T | A^T]: row c has ones at (c - b_t) mod l and l + (c - a_t) mod l.
     // Edge positions follow the polynomial terms, so that lanes reading the
     // same position touch consecutive posteriors (the order does not change
@@ -436,6 +638,8 @@ int sagms_graph_info(sagms_graph gh, sagms_graph_info_t* info) {
     info->dv_max = g->dv_max;
     info->words_n = g->wn;
     info->words_m = g->wm;
+    info->joint = g->joint ? 1 : 0;
+    info->words_e = g->we;
     return SAGMS_OK;
 }
 
@@ -507,6 +711,11 @@ int sagms_derive_gains(double l0, int32_t dc, double ratio, double eta, sagms_de
     cfg->alpha_min = ratio * amax;
     cfg->eta = e;
     return SAGMS_OK;
+}
+
+float sagms_depolarizing_llr(double p) {
+    if (!(p > 0.0 && p < 0.75)) return NAN;
+    return (float)std::log((1.0 - p) / (p / 3.0));
 }
 
 float sagms_prior_llr(double p) {

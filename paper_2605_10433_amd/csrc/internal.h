@@ -76,6 +76,27 @@ struct DecodeLayout {
     int cw, zero, post0, padpost, gain0, words;
 };
 
+// Joint (quaternary) decode kernels: shapes X(index, DC, DV, CPL, VPL) with
+// DV = 2 * DVH, ranks [0, DVH) of a variable being its X-type checks and
+// [DVH, DV) its Z-type checks (shorter halves padded).
+#define SAGMS_JOINT_SHAPES(X) \
+    X(0, 4, 4, 1, 1)          \
+    X(1, 6, 6, 1, 1)          \
+    X(2, 10, 10, 2, 2)        \
+    X(3, 10, 10, 4, 4)
+constexpr int kNumJointShapes = 4;
+
+// Per-wave LDS layout of the joint kernel, in 32-bit words:
+//   c2v slots  [dc][cw]        slot(c, p) = p * cw + c  (cw = 64 * cpl)
+//   zero       [64]            0.0f (padding of short variable halves)
+//   pairx      [64 * vpl] x 2  (A, W) of variable j for its X-type checks
+//   pairz      [64 * vpl] x 2  (A, W) of variable j for its Z-type checks
+//   padpair    [64] x 2        (+inf, +0) (padding of short checks)
+//   gains      [2 * (cw + 1)]  gain pairs by residual weight
+struct JointLayout {
+    int cw, zero, pairx, pairz, padpair, gain0, words;
+};
+
 // Gain law of a decoder configuration (eq. (alphaeff)): kind MS / BP (gain
 // 1), SMS (alpha), SAGMS (alpha_min, alpha_max, eta).  The kernels evaluate
 // it per residual weight w in IEEE double, operation by operation, and round
@@ -132,6 +153,13 @@ struct DeviceTables {
 
 struct Graph {
     int m = 0, n = 0, E = 0, dc_max = 0, dv_max = 0, k = -1, wn = 0, wm = 0;
+    // joint graph: checks 0 .. m/2 - 1 are X-type rows (Pauli X), the rest
+    // Z-type rows (Pauli Z); error and estimate vectors are (x | z) halves of
+    // wn words each (we = 2 wn words); rows_bits is [m][we]; logicals holds
+    // 2k rows (u | v) whose parity u.r_x + v.r_z flags a logical failure
+    bool joint = false;
+    int we = 0;
+    int dvh = 0;  // joint: the larger of a variable's X-type and Z-type degrees
     // decoding matrix H: row i has columns cols[row_ptr[i] .. row_ptr[i+1]-1] in
     // the order used as the check's edge positions
     std::vector<int> row_ptr, cols;
@@ -148,6 +176,7 @@ struct Graph {
     DecodeShape shape{};
     DecodeLayout layout{};
     std::vector<uint32_t> cn_addr_host, vn_addr_host;
+    JointLayout jlayout{};  // joint graphs
     LayeredHost layered;
     std::mutex mu;
     DeviceTables dev[kMaxDevices];
@@ -168,6 +197,30 @@ void plan_layers(Graph* g);
 // Shape selection for the decode kernels.
 bool pick_shape(int m, int n, int dc, int dv, DecodeShape* out);
 DecodeLayout make_layout(const DecodeShape& s);
+
+// Shape selection for the joint kernels; layout of a joint shape.
+bool pick_joint_shape(int m, int n, int dc, int dvh, DecodeShape* out);
+JointLayout make_joint_layout(const DecodeShape& s);
+
+// Arguments of the joint decode kernel.
+struct JointArgs {
+    const uint64_t* synd;
+    const float* llr0;
+    GainLaw gains;
+    const uint32_t* cn_addr;  // [cpl * dc][64] LDS word index of the (A, W) pair read at (check, pos)
+    const uint32_t* vn_addr;  // [vpl * dv][64] LDS word index of the c2v slot read at (var, rank)
+    uint64_t* ehat;           // [nframes][2 wn]: x-hat words, then z-hat words
+    int32_t* iters;
+    uint8_t* conv;
+    float* gamma;             // optional [nframes][n][3] last beliefs (X, Y, Z)
+    int64_t nframes;
+    int m, n, wm, wn, lmax, frames_per_wave;
+    JointLayout L;
+};
+int launch_joint(const DecodeShape& s, const JointArgs& a, hipStream_t st);
+// Waves of a kernel resident on the current device (occupancy x compute
+// units), queried once per kernel and device (decode.hip).
+int resident_waves(const void* kernel, int wpb, size_t lds, int64_t* out);
 
 // Kernel launchers (one translation unit each).
 struct DecodeArgs {
@@ -309,11 +362,13 @@ struct SampleArgs {
     uint32_t stream_id;
     uint32_t tx, ty, tz;
     int m, n, dc, wn, wm, frames_per_wave, lanes_per_frame;
+    int joint;  // rows / columns over the (x | z) planes: rows of 2 wn words, columns j < n in x, n + j in z
 };
 int launch_sample(const SampleArgs& a, hipStream_t st);
 
 struct JudgeArgs {
     const uint64_t* ex;
+    const uint64_t* ez;  // joint graphs: the Z plane (words wplane .. wn - 1 of the residual); else null
     const uint64_t* ehat;
     const uint8_t* conv;
     const int32_t* iters;
@@ -321,7 +376,8 @@ struct JudgeArgs {
     uint8_t* fail;
     uint64_t* counters;
     int64_t nframes;
-    int k, wn;
+    int k, wn;   // basis rows; words per residual (= per e_hat frame)
+    int wplane;  // words per frame of ex (and ez)
 };
 int launch_judge(const JudgeArgs& a, hipStream_t st);
 

@@ -1,6 +1,9 @@
 // Logical-failure judge: frame f fails iff it did not converge or the
 // residual r = e_x xor e_hat has odd overlap with a row of the logical basis
 // (a basis of ker(H_other) modulo rowspace(H)), i.e. r is not a stabilizer.
+// Joint graphs: r = (e_x | e_z) xor (x_hat | z_hat) against rows (u | v)
+// whose overlap u.r_x + v.r_z is the symplectic product with a logical
+// operator.
 // A bounded grid of blocks strides over the frames, kJudgeUnroll frames per
 // thread at a time with all their loads issued before any is used: the
 // residual words stay in registers, the basis is staged in LDS (read at
@@ -17,13 +20,18 @@ constexpr int kJudgeBlock = 1024;
 constexpr int kJudgeMaxBlocks = 256;
 constexpr size_t kJudgeLdsMax = 32768;
 
+// Word w of frame f's error: the X plane, then (joint graphs) the Z plane.
+__device__ __forceinline__ uint64_t error_word(const JudgeArgs& a, int64_t f, int w) {
+    return w < a.wplane ? a.ex[f * a.wplane + w] : a.ez[f * a.wplane + (w - a.wplane)];
+}
+
 __device__ __forceinline__ bool judge_frame_any(const JudgeArgs& a, int64_t f) {
-    const uint64_t* x = a.ex + f * a.wn;
     const uint64_t* e = a.ehat + f * a.wn;
     uint32_t odd = 0;
     for (int t = 0; t < a.k; ++t) {
         uint32_t cnt = 0;
-        for (int w = 0; w < a.wn; ++w) cnt += __builtin_popcountll((x[w] ^ e[w]) & a.logicals[(size_t)t * a.wn + w]);
+        for (int w = 0; w < a.wn; ++w)
+            cnt += __builtin_popcountll((error_word(a, f, w) ^ e[w]) & a.logicals[(size_t)t * a.wn + w]);
         odd |= cnt;
     }
     return a.conv[f] == 0 || (odd & 1u);
@@ -69,7 +77,7 @@ __global__ void __launch_bounds__(kJudgeBlock) judge_kernel(JudgeArgs a) {
                 const bool in = f < a.nframes;
 #pragma unroll
                 for (int w = 0; w < WN; ++w)
-                    r[u][w] = in && w < a.wn ? a.ex[f * a.wn + w] ^ a.ehat[f * a.wn + w] : 0ull;
+                    r[u][w] = in && w < a.wn ? error_word(a, f, w) ^ a.ehat[f * a.wn + w] : 0ull;
                 conv[u] = in ? a.conv[f] : 1;
                 it[u] = in ? a.iters[f] : 0;
             }

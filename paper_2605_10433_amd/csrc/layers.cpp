@@ -24,6 +24,7 @@ static int refuse(LayeredHost* lh, const char* why) {
 }
 
 static int plan(const Graph* g, LayeredHost* lh) {
+    if (g->joint) return refuse(lh, "layered schedule: joint graphs decode with the flooding schedule");
     const int m = g->m, n = g->n;
     const int dc = g->row_ptr[1] - g->row_ptr[0];
     for (int c = 0; c < m; ++c)

@@ -81,9 +81,11 @@ __device__ __forceinline__ void zero_tail(const SampleArgs& a, unsigned char* xb
         for (int q = q0 + lane; q < nq; q += 64) xb[(size_t)fs * nq + q] = 0;
 }
 
-// Small codes: n <= 64 * WN, m <= 64 * CPLS, rows of H in registers.
-template <int WN, int CPLS>
+// Small codes: n <= 64 * WN, m <= 64 * CPLS, rows of H in registers
+// (JOINT: rows of 2 WN words over the (x | z) planes).
+template <int WN, int CPLS, bool JOINT = false>
 __global__ void __launch_bounds__(64 * kSampleWavesPerBlock) sample_kernel_rows(SampleArgs a) {
+    constexpr int RW = JOINT ? 2 * WN : WN;  // words per row
     extern __shared__ unsigned char slds[];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -97,12 +99,16 @@ __global__ void __launch_bounds__(64 * kSampleWavesPerBlock) sample_kernel_rows(
     const int64_t f_end = min(f_begin + (int64_t)a.frames_per_wave, a.nframes);
 
     zero_tail(a, xb, nq, lane);
-    uint64_t row[CPLS][WN];
+    uint64_t row[CPLS][RW];
+    const int rwords = JOINT ? 2 * a.wn : a.wn;
 #pragma unroll
     for (int k = 0; k < CPLS; ++k) {
         const int c = 64 * k + lane;
 #pragma unroll
-        for (int w = 0; w < WN; ++w) row[k][w] = (c < a.m && w < a.wn) ? a.rows[(size_t)c * a.wn + w] : 0ull;
+        for (int w = 0; w < RW; ++w) {
+            const int pw = JOINT && w >= WN ? a.wn + (w - WN) : w;  // word of the row in the graph's table
+            row[k][w] = (c < a.m && (w % WN) < a.wn) ? a.rows[(size_t)c * rwords + pw] : 0ull;
+        }
     }
 
     for (int64_t fb = f_begin; fb < f_end; fb += fpp) {
@@ -110,15 +116,15 @@ __global__ void __launch_bounds__(64 * kSampleWavesPerBlock) sample_kernel_rows(
         wave_lds_sync_s();
         for (int fs = 0; fs < fpp && fb + fs < f_end; ++fs) {
             const int64_t f = fb + fs;
-            uint64_t wx[WN];
+            uint64_t wx[WN], wzs[WN];
             uint64_t myx = 0, myz = 0, mys = 0;
 #pragma unroll
             for (int w = 0; w < WN; ++w) {
                 wx[w] = __builtin_amdgcn_ballot_w64(xb[(size_t)fs * nq + 64 * w + lane] != 0);
-                const uint64_t wz = __builtin_amdgcn_ballot_w64(zb[(size_t)fs * nq + 64 * w + lane] != 0);
+                wzs[w] = __builtin_amdgcn_ballot_w64(zb[(size_t)fs * nq + 64 * w + lane] != 0);
                 if (lane == w) {
                     myx = wx[w];
-                    myz = wz;
+                    myz = wzs[w];
                 }
             }
 #pragma unroll
@@ -126,6 +132,10 @@ __global__ void __launch_bounds__(64 * kSampleWavesPerBlock) sample_kernel_rows(
                 uint32_t cnt = 0;
 #pragma unroll
                 for (int w = 0; w < WN; ++w) cnt += __builtin_popcountll(row[k][w] & wx[w]);
+                if constexpr (JOINT) {
+#pragma unroll
+                    for (int w = 0; w < WN; ++w) cnt += __builtin_popcountll(row[k][WN + w] & wzs[w]);
+                }
                 const uint64_t ws = __builtin_amdgcn_ballot_w64(cnt & 1u);
                 if (lane == k) mys = ws;
             }
@@ -178,9 +188,10 @@ __global__ void __launch_bounds__(64 * kSampleWavesPerBlock) sample_kernel_gathe
                 uint32_t par = 0;
                 if (c < a.m) {
                     const uint16_t* rc = cols + (size_t)c * a.dc;
+                    const unsigned char* z = zb + (size_t)fs * nq;
                     for (int p = 0; p < a.dc; ++p) {
-                        const uint16_t j = rc[p];
-                        if (j != 0xFFFF) par ^= x[j];
+                        const uint16_t j = rc[p];  // joint graphs: n + j is byte j of the Z plane
+                        if (j != 0xFFFF) par ^= j < a.n ? x[j] : z[j - a.n];
                     }
                 }
                 const uint64_t ws = __builtin_amdgcn_ballot_w64(par & 1u);
@@ -210,13 +221,25 @@ int launch_sample(const SampleArgs& a0, hipStream_t st) {
         SAGMS_HIP(hipGetLastError());                                                                      \
         return SAGMS_OK;                                                                                   \
     }
-    if (a.rows) {
+#define ROWS_J(WN, CPLS)                                                                                  \
+    if (a.wn <= WN && a.wm <= CPLS) {                                                                      \
+        size_t lds = (size_t)kSampleWavesPerBlock * 2 * fpp * 64 * WN;                                     \
+        hipLaunchKernelGGL((sample_kernel_rows<WN, CPLS, true>), grid, block, lds, st, a);                \
+        SAGMS_HIP(hipGetLastError());                                                                      \
+        return SAGMS_OK;                                                                                   \
+    }
+    if (a.rows && a.joint) {
+        ROWS_J(1, 1)
+        ROWS_J(2, 2)
+        ROWS_J(4, 4)
+    } else if (a.rows) {
         ROWS(1, 1)
         ROWS(2, 1)
         ROWS(4, 2)
         ROWS(8, 4)
     }
 #undef ROWS
+#undef ROWS_J
     if (a.n > 0xFFFF) return fail(SAGMS_EUNSUPPORTED, "sampler supports n < 65535");
     size_t cols_bytes = ((size_t)a.m * a.dc * 2 + 15) & ~(size_t)15;
     size_t lds = cols_bytes + (size_t)kSampleWavesPerBlock * 2 * fpp * 64 * a.wn;

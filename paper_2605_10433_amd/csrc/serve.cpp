@@ -288,6 +288,7 @@ int sagms_server_create(const sagms_graph* graphs, const float* const* llr0_host
         Graph* g = reinterpret_cast<Graph*>(graphs[c]);
         if (!g) return fail(SAGMS_EINVAL, "code %d: null graph", c);
         if (!llr0_host[c]) return fail(SAGMS_EINVAL, "code %d: null prior", c);
+        if (g->joint) return fail(SAGMS_EUNSUPPORTED, "code %d: joint graphs decode through sagms_decode only", c);
         if (!g->shape_ok || mixed_tier_of_shape(shape_index(g->shape)) < 0)
             return fail(SAGMS_EUNSUPPORTED, "code %d: no decode kernel fits it", c);
     }

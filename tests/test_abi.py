@@ -48,6 +48,66 @@ def test_small_gb_codes(code):
     assert (channel.unpack(g.rows(), g.n) == hz).all()
 
 
+JOINT_CODES = [("L7", (7, [0, 1], [0, 2])), ("L7b", (7, [0, 1, 3], [0, 2, 6])), ("G63", None), ("G127", None)]
+
+
+@pytest.mark.parametrize("name,spec", JOINT_CODES)
+def test_joint_graph_matches_oracle(name, spec):
+    """The joint graph against the oracle's quaternary matrix of the same GB
+    code (X-type rows of H_X, then Z-type rows of H_Z): sizes, degrees, the
+    rows as (x | z) halves, and 2k logical rows (u | v) that commute with
+    every row and are independent modulo the stabilizer group."""
+    from oracle import joint
+    l, a, b = spec if spec else workloads.code(name)
+    g = sagms.Graph.gb_joint(l, a, b)
+    sx, sz, _ = joint.gb_joint(l, a, b)
+    n = 2 * l
+    assert (g.m, g.n, g.n_edges, g.joint) == (2 * l, n, int((sx | sz).sum()), 1)
+    assert (g.dc_max, g.dv_max) == (len(a) + len(b), len(a) + len(b))
+    assert (g.words_n, g.words_m, g.words_e) == ((n + 63) // 64, (2 * l + 63) // 64, 2 * ((n + 63) // 64))
+    rows = g.rows()
+    wn = g.words_n
+    assert (channel.unpack(rows[:, :wn], n) == sz).all() and (channel.unpack(rows[:, wn:], n) == sx).all()
+    hx, hz = codes.gb_matrices(l, a, b)
+    k = codes.dimension(hx, hz)
+    assert g.k == k
+    lg = g.logicals()
+    assert lg.shape == (2 * k, 2 * wn)
+    u = channel.unpack(lg[:, :wn], n).astype(np.int64)
+    v = channel.unpack(lg[:, wn:], n).astype(np.int64)
+    # row (u | v) flags r when u.r_x + v.r_z is odd: the logical operator is
+    # L = (x part v, z part u); it commutes with every row: S_x.L_z + S_z.L_x = 0
+    assert not ((sx.astype(np.int64) @ u.T + sz.astype(np.int64) @ v.T) & 1).any()
+    stab = np.hstack([sx, sz])
+    ops = np.hstack([v, u]).astype(np.uint8)
+    assert gf2.rank(np.vstack([stab, ops])) == gf2.rank(stab) + 2 * k
+    assert not u[k:].any() and not v[:k].any()       # Z-type logicals first, then X-type
+
+
+def test_joint_graph_argument_checks():
+    L = sagms.lib()
+    g = sagms.Graph.gb_joint(*workloads.code("G63"))
+    fake = ctypes.c_void_p(0x1000)
+    for kind, prec, sched in (("bp", "fp32", "flooding"), ("sagms", "fp16", "flooding"),
+                              ("sagms", "fp32", "layered"), ("ms", "int6", "flooding")):
+        cfg = sagms.decoder_config(kind, precision=prec, schedule=sched)
+        assert L.sagms_decode(g._h, fake, fake, ctypes.byref(cfg), 4, fake, fake, fake, None) == sagms.EUNSUPPORTED
+    # the binary judge refuses a joint graph, the joint judge a binary one
+    assert L.sagms_judge(g._h, fake, fake, fake, fake, 4, None, fake, None) == sagms.EINVAL
+    gb = sagms.Graph.gb(*workloads.code("G63"))
+    assert L.sagms_judge_joint(gb._h, fake, fake, fake, fake, fake, 4, None, fake, None) == sagms.EINVAL
+    # the joint sampler needs the Z plane
+    assert L.sagms_gen_errors(g._h, 1, 0, 0, 4, 0.05, fake, None, fake, None) == sagms.EINVAL
+    # batches and servers refuse joint graphs
+    seg = (sagms.Segment * 1)()
+    seg[0].graph, seg[0].nframes = g._h.value, 4
+    seg[0].synd = seg[0].llr0 = seg[0].ehat = seg[0].iters = seg[0].converged = 0x1000
+    out = ctypes.c_void_p()
+    cfg = sagms.decoder_config("sagms")
+    assert L.sagms_batch_create(ctypes.cast(seg, ctypes.c_void_p), 1, ctypes.byref(cfg),
+                                ctypes.byref(out)) == sagms.EUNSUPPORTED
+
+
 def test_build_graph_from_dense_matches_gb():
     hx, hz = codes.gb_matrices(**codes.G63)
     g = sagms.Graph.from_dense(hz, hx)
