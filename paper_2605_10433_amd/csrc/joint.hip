@@ -69,8 +69,10 @@ __device__ __forceinline__ JointVar joint_var(float l0, float sx, float sz) {
     return v;
 }
 
+// At most 128 VGPRs: four resident wavefronts per SIMD.
 template <int DC, int DV, int CPL, int VPL>
-__global__ void __launch_bounds__(64 * kJointWavesPerBlock) joint_kernel(JointArgs a, WaveSchedule ws) {
+__global__ void __launch_bounds__(64 * kJointWavesPerBlock) __attribute__((amdgpu_waves_per_eu(4)))
+joint_kernel(JointArgs a, WaveSchedule ws) {
     using LY = JLay<DC, DV, CPL, VPL>;
     constexpr int DVH = DV / 2;
     extern __shared__ float jlds_all[];
@@ -141,13 +143,14 @@ __global__ void __launch_bounds__(64 * kJointWavesPerBlock) joint_kernel(JointAr
                 float2 pw[DC];
 #pragma unroll
                 for (int p = 0; p < DC; ++p) pw[p] = *reinterpret_cast<const float2*>(lds + caddr[k][p]);
-                uint32_t dec = sb[k];
+                float wv[DC];
 #pragma unroll
                 for (int p = 0; p < DC; ++p) {
                     v[k][p] = (pw[p].x - c2v[k][p]) + fabsf(pw[p].y);
-                    dec ^= bits(pw[p].y);
+                    wv[p] = pw[p].y;
                 }
-                unsat[k] = (int32_t)dec < 0;
+                // the decision bits ride in the sign bits of the W's
+                unsat[k] = (int32_t)xor_signs<DC>(wv, sb[k]) < 0;
                 w += __builtin_popcountll(ballot(unsat[k]));
             }
             if (w == 0) {

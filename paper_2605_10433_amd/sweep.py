@@ -3,7 +3,7 @@
     python -m paper_2605_10433_amd.sweep [--code G63] [--p 0.02,0.03,...]
         [--decoders ms,sms0.5,...,sagms,sagms-derived,bp] [--lmax 100]
         [--frames 1048576 | --until-failures 500 --max-frames 20000000]
-        [--p0 0.1] [--ratio-ref sms0.5]
+        [--p0 0.1] [--ratio-ref sms0.5] [--joint]
 
 For every noise level p and decoder: Philox frames of the depolarizing
 channel (seed 1, stream = index of p in the grid, the same frames for every
@@ -18,7 +18,10 @@ the layered schedule (SAGMS_LAYERED).  Prints one JSON
 line per point (FER with its 95 % Wilson interval, mean and 99th-percentile
 round count, decode and end-to-end frames/s, and with --ratio-ref the FER
 ratio to that decoder with its 95 % log-method interval) and a markdown
-table at the end.
+table at the end.  --joint decodes X and Z together on the code's joint
+graph (X- and Z-type rows; sagms_build_gb_joint) with the prior
+ln((1 - p) / (p / 3)) of the paper's Section II, judged by sagms_judge_joint
+(MS, SMS and SAGMS decoders).
 """
 from __future__ import annotations
 
@@ -63,7 +66,8 @@ def make_config(name, g, l0, lmax):
 def run_point(g, code, p, stream_id, name, lmax, frames=None, until_failures=None, max_frames=None, p0=None,
               seed=1):
     import torch
-    l0 = sagms.prior_llr(p0 if p0 is not None else p)
+    joint = bool(g.joint)
+    l0 = (sagms.depolarizing_llr if joint else sagms.prior_llr)(p0 if p0 is not None else p)
     cfg = make_config(name, g, l0, lmax)
     cap = frames if frames is not None else max_frames
     buf = sagms.frame_buffers(g, min(CHUNK, cap))
@@ -81,7 +85,10 @@ def run_point(g, code, p, stream_id, name, lmax, frames=None, until_failures=Non
         ev[1].record()
         sagms.decode(g, b["synd"], llr, cfg, b["ehat"], b["iters"], b["converged"])
         ev[2].record()
-        sagms.judge(g, b["ex"], b["ehat"], b["converged"], b["iters"], counters)
+        if joint:
+            sagms.judge_joint(g, b["ex"], b["ez"], b["ehat"], b["converged"], b["iters"], counters)
+        else:
+            sagms.judge(g, b["ex"], b["ehat"], b["converged"], b["iters"], counters)
         ev[3].record()
         hist += torch.bincount(b["iters"].long(), minlength=lmax + 1)
         torch.cuda.synchronize()
@@ -94,7 +101,8 @@ def run_point(g, code, p, stream_id, name, lmax, frames=None, until_failures=Non
     h = hist.cpu().numpy()
     p99 = int(np.searchsorted(np.cumsum(h), 0.99 * done))
     lo, hi = wilson(fails, done)
-    r = {"code": code, "p": p, "decoder": name, "frames": done, "lmax": lmax, "failures": fails,
+    r = {"code": code + (" joint" if joint else ""), "p": p, "decoder": name, "frames": done, "lmax": lmax,
+         "failures": fails,
          "fer": fails / done, "fer_wilson95": [lo, hi], "mean_iters": isum / done, "p99_iters": p99,
          "decode_ms": dec_ms, "decode_frames_per_s": done / (dec_ms * 1e-3),
          "step_frames_per_s": done / (tot_ms * 1e-3),
@@ -119,12 +127,13 @@ def main():
     ap.add_argument("--decoders", default="ms,sms0.5,sms0.625,sms0.75,sms0.875,sagms,bp")
     ap.add_argument("--ratio-ref", default=None, help="report each decoder's FER ratio to this decoder")
     ap.add_argument("--lmax", type=int, default=workloads.SWEEP_LMAX)
+    ap.add_argument("--joint", action="store_true", help="decode X and Z jointly on the code's joint graph")
     args = ap.parse_args()
     if args.frames is None and args.until_failures is None:
         args.frames = workloads.SWEEP_FRAMES
     import torch
     torch.cuda.set_device(0)
-    g = sagms.Graph.gb(*workloads.code(args.code))
+    g = (sagms.Graph.gb_joint if args.joint else sagms.Graph.gb)(*workloads.code(args.code))
     # warm-up: build device tables and gain tables, first launches
     run_point(g, args.code, 0.05, 0, "sagms", 10, frames=4096)
     rows = []
