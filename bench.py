@@ -71,6 +71,29 @@ def measured_traffic(frames, p):
     return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
 
 
+# rocprofv3 counters of the decode kernel on the same workload (VALU issue and
+# LDS index-unit activity over the busy cycles of every SIMD / CU); used only
+# while the decode sources are those the counters were taken with.
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "decode_g63_sagms_p005_counters.json")
+# The survey's algorithmic count of lane operations per edge-update, fixed
+# before any tuning (reported beside the tuned count of 8).
+OPS_PER_EDGE_UPDATE_SURVEY = 14
+
+
+def measured_counters(frames, p):
+    """Counter-derived roofline fractions of the decode kernel from the
+    committed record, or None."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    rec = json.load(open(COUNTERS_FILE))
+    if (rec.get("decode_source_sha256") != decode_source_sha256() or rec.get("frames_per_launch") != frames
+            or rec.get("p") != p):
+        return None
+    return {k: rec[k] for k in ("valu_issue_frac", "lds_idx_active_frac", "valu_per_frame_round",
+                                "lds_bank_conflict_cycles_per_lds_instruction", "sustained_clock_ghz")
+            if k in rec}
+
+
 def copy_calibration(nbytes=1 << 30, reps=4):
     """A plain device copy of known size, for scaling the FETCH_SIZE /
     WRITE_SIZE counters: each dispatch reads and writes nbytes."""
@@ -317,7 +340,7 @@ def run_mix(args):
     plan = batch.get_plan().as_dict()
     out = {
         "metric": "%s frames/s" % args.decoder.upper(),
-        "value": frames / (total_ms * 1e-3),
+        "value": value,
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -356,6 +379,18 @@ def run_serve(args):
     at the offered loads (fractions of the serving-format batch throughput),
     replayed in real time by the server; one JSON line per load with p50 /
     p99 latency and served throughput beside the FP32 batch."""
+    for out in serve_measure(args, workloads_serve_loads()):
+        print(json.dumps(out), flush=True)
+
+
+def workloads_serve_loads():
+    import workloads
+    return list(workloads.SERVE_LOADS)
+
+
+def serve_measure(args, loads):
+    """The serving measurement of run_serve at the given offered loads; returns
+    one record per load."""
     import torch
 
     import paper_2605_10433_amd as sagms
@@ -443,7 +478,8 @@ def run_serve(args):
             reqs["converged"][sel] = conv.ctypes.data + lo
         return dict(reqs=reqs, arrive=arrive, code=code, size=size, keep=keep)
 
-    for li, load in enumerate(workloads.SERVE_LOADS):
+    records = []
+    for li, load in enumerate(loads):
         rate = load * batch_fps / mean_frames
         # a 50 ms warm-up trace at the same load is replayed right before the
         # timed one, so that the timed trace starts on a busy, clocked-up GPU
@@ -499,9 +535,10 @@ def run_serve(args):
                        "tile_frames": args.serve_tile, "min_launch_frames": args.serve_min_frames,
                        "max_wait_us": args.serve_max_wait_us},
         }
-        print(json.dumps(out), flush=True)
+        records.append(out)
         del tr
     srv.close()
+    return records
 
 
 def main():
@@ -544,6 +581,9 @@ def main():
                     help="run sampling, decoding and the judge of each step in one stream (default for the "
                          "mixed-code workload, whose persistent decode already fills the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="single-code workload: skip the FP16 pass and the serving measurement that follow the "
+                         "timed steps (for short profiler runs)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the oracle (MS, SMS 0.75, SAGMS; 2^16 frames; one core and all cores)")
     ap.add_argument("--source-sha", action="store_true", help="only print the decode sources' SHA-256")
@@ -603,9 +643,9 @@ def main():
     bufs = [sagms.frame_buffers(g, nf, device=dev) for _ in range(2 if args.pipeline else 1)]
     llr = torch.full((g.n,), sagms.depolarizing_llr(p) if joint else sagms.prior_llr(p), dtype=torch.float32,
                      device=dev)
-    judge = (lambda buf, **kw: sagms.judge_joint(g, buf["ex"], buf["ez"], buf["ehat"], buf["converged"],
-                                                  buf["iters"], counters, **kw)) if joint else \
-        (lambda buf, **kw: sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], counters, **kw))
+    judge = (lambda buf, ctr, **kw: sagms.judge_joint(g, buf["ex"], buf["ez"], buf["ehat"], buf["converged"],
+                                                       buf["iters"], ctr, **kw)) if joint else \
+        (lambda buf, ctr, **kw: sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], ctr, **kw))
     cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, frames_per_wave=args.frames_per_wave,
                                schedule=args.schedule, **workloads.SAGMS_PARAMS)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
@@ -629,7 +669,7 @@ def main():
                          bufs[b]["synd"], stream=side)
         sampled[b].record(side)
 
-    def step(s, ev=None, next_s=None):
+    def step(s, cfg, ctr, ev=None, next_s=None):
         b = s % len(bufs)
         buf = bufs[b]
         if side is None:
@@ -644,39 +684,43 @@ def main():
         if ev is not None:
             ev[1].record(stream)
         if side is None:
-            judge(buf)
+            judge(buf, ctr)
             judged[b].record(stream)
         else:
             # the judge runs on the second stream too, beside the next decode,
             # so the decode stream runs decodes back to back
             decoded[b].record(stream)
             side.wait_event(decoded[b])
-            judge(buf, stream=side)
+            judge(buf, ctr, stream=side)
             judged[b].record(side)
 
-    for s in range(args.warmup):
-        if side is not None and s == 0:
-            sample(args.steps)
-        step(args.steps + s, next_s=args.steps + s + 1 if s + 1 < args.warmup else None)
-    torch.cuda.synchronize()
-    counters.zero_()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    t_start.record(stream)
-    if side is not None:  # the first sampling is part of the timed region
-        side.wait_event(t_start)
-        sample(0)
-    for s in range(args.steps):
-        step(s, events[s], next_s=s + 1 if s + 1 < args.steps else None)
-    if side is not None:  # the last judge is part of the timed region
-        stream.wait_event(judged[(args.steps - 1) % len(bufs)])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    total_ms = t_start.elapsed_time(t_end)
-    dec_ms = [e0.elapsed_time(e1) for e0, e1 in events]
+    def timed_run(cfg, ctr, warmup):
+        """warmup untimed steps (frames beyond the timed ones), then the timed
+        steps 0 .. steps - 1; returns (total ms, decode ms per step, wall s)."""
+        for s in range(warmup):
+            if side is not None and s == 0:
+                sample(args.steps)
+            step(args.steps + s, cfg, ctr, next_s=args.steps + s + 1 if s + 1 < warmup else None)
+        torch.cuda.synchronize()
+        ctr.zero_()
+        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+        t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t_start.record(stream)
+        if side is not None:  # the first sampling is part of the timed region
+            side.wait_event(t_start)
+            sample(0)
+        for s in range(args.steps):
+            step(s, cfg, ctr, events[s], next_s=s + 1 if s + 1 < args.steps else None)
+        if side is not None:  # the last judge is part of the timed region
+            stream.wait_event(judged[(args.steps - 1) % len(bufs)])
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        return t_start.elapsed_time(t_end), [e0.elapsed_time(e1) for e0, e1 in events], time.perf_counter() - w0
+
+    total_ms, dec_ms, wall = timed_run(cfg, counters, args.warmup)
     c = counters.cpu().numpy()
     frames = nf * args.steps
     sum_iters = int(c[1])
@@ -698,9 +742,40 @@ def main():
     mean_dec_ms = float(np.mean(dec_ms))
     ops_per_launch = ops_per_edge * edge_updates / args.steps
     achieved = ops_per_launch / (mean_dec_ms * 1e-3) / 1e12
+    achieved_survey = OPS_PER_EDGE_UPDATE_SURVEY * edge_updates / args.steps / (mean_dec_ms * 1e-3) / 1e12
+    p99_last = float(torch.quantile(it_last, 0.99).item())
     from paper_2605_10433_amd.stats import wilson
     fer = c[0] / frames
     lo, hi = wilson(int(c[0]), frames)
+    value = frames / (total_ms * 1e-3)
+    default_workload = args.graph == "gb" and args.decoder == "sagms" and args.schedule == "flooding"
+    extras = default_workload and not args.no_extras
+    fp16 = serving = None
+    if extras:
+        # FP16 messages (FP32 posteriors) over the same timed frames: throughput
+        # beside FP32 at the same p, with the FER of both on those frames
+        cfg16 = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha,
+                                     frames_per_wave=args.frames_per_wave, precision="fp16", **workloads.SAGMS_PARAMS)
+        ctr16 = torch.zeros(2, dtype=torch.int64, device=dev)
+        t16, d16, _ = timed_run(cfg16, ctr16, 5)
+        c16 = ctr16.cpu().numpy()
+        lo16, hi16 = wilson(int(c16[0]), frames)
+        fer16 = c16[0] / frames
+        fp16 = {"value": frames / (t16 * 1e-3), "unit": "frames/s", "ms_per_step": t16 / args.steps,
+                "decode_ms_per_step": float(np.mean(d16)), "decode_frames_per_s": nf / (float(np.mean(d16)) * 1e-3),
+                "vs_fp32": frames / (t16 * 1e-3) / value, "fer": fer16, "fer_wilson95": [lo16, hi16],
+                "mean_iters": c16[1] / frames,
+                "fer_in_fp32_interval": bool(lo <= fer16 <= hi), "fp32_fer_in_fp16_interval": bool(lo16 <= fer <= hi16),
+                "frames": "the timed steps' frames, decoded again with FP16 messages (FP32 posteriors)"}
+        # the five-code serving workload at 80 % of the FP16 batch throughput
+        import copy
+        sargs = copy.copy(args)
+        sargs.precision, sargs.decoder = "fp16", "sagms"
+        rec = serve_measure(sargs, [0.8])[0]
+        serving = {k: rec[k] for k in ("p50_us", "p99_us", "mean_us", "offered_load", "offered_frames_per_s",
+                                       "served_frames_per_s", "batch_frames_per_s", "fp32_batch_frames_per_s",
+                                       "requests", "frames")}
+        serving["workload"] = rec["config"]["workload"]
     out = {
         "metric": "SAGMS frames/s",
         "value": frames / (total_ms * 1e-3),
@@ -725,7 +800,7 @@ def main():
         "decode_ms_per_step": mean_dec_ms,
         "decode_frames_per_s": nf / (mean_dec_ms * 1e-3),
         "mean_iters": sum_iters / frames,
-        "p99_iters_last_step": float(torch.quantile(it_last, 0.99).item()),
+        "p99_iters_last_step": p99_last,
         "fer": fer,
         "fer_wilson95": [lo, hi],
         "wall_s": wall,
@@ -735,10 +810,16 @@ def main():
                                                             and args.schedule == "flooding") else None,
                      "kernel": kernel,
                      "ops_per_edge_update": ops_per_edge,
+                     "frac_survey_14_ops": None if joint else achieved_survey / VALU_PEAK_TOPS,
+                     "counters": measured_counters(nf, p) if default_workload else None,
                      "note": "decode launch time inside the pipelined steps (the next step's sampler and the previous step's judge share the GPU)"
                              if args.pipeline else "decode launch time, one stream",
                      "isolated": {"decode_ms": iso_ms, "achieved": iso_achieved, "frac": iso_achieved / VALU_PEAK_TOPS}},
     }
+    if fp16 is not None:
+        out["fp16"] = fp16
+    if serving is not None:
+        out["serving_p80"] = serving
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.lmax, workloads.SAGMS_PARAMS, graph=args.graph if joint else "gb")
     print(json.dumps(out), flush=True)
