@@ -340,7 +340,7 @@ def run_mix(args):
     plan = batch.get_plan().as_dict()
     out = {
         "metric": "%s frames/s" % args.decoder.upper(),
-        "value": value,
+        "value": frames / (total_ms * 1e-3),
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": args.steps,

@@ -352,12 +352,14 @@ typedef struct {
  *   PER_CODE  one sagms_decode launch per segment, tile_frames frames per
  *             wave
  * waves_per_block (1, 2 or 4), blocks_per_cu (0 = as many as fit, else
- * 1..64) and reg_budget (0 = the compiler's register allocation, 1 = a
+ * 1..64), reg_budget (0 = the compiler's register allocation, 1 = a
  * tighter one allowing one more resident wave per SIMD for the register
- * classes that have one compiled, the compiler's for the others) apply to
- * the persistent plans; a code class whose LDS slices would exceed 64 KiB
- * per block runs with waves_per_block halved until they fit.  Results never
- * depend on the plan. */
+ * classes that have one compiled, the compiler's for the others) and unroll
+ * (decoding rounds per iteration of a wave's round loop: 1 or 2, 0 reads as
+ * 1; every round keeps its own exit test) apply to the persistent plans; a
+ * code class whose LDS slices would exceed 64 KiB per block runs with
+ * waves_per_block halved until they fit.  Results never depend on the
+ * plan. */
 typedef enum { SAGMS_PLAN_SINGLE = 0, SAGMS_PLAN_TIERED = 1, SAGMS_PLAN_PER_CODE = 2 } sagms_plan_kind;
 
 typedef struct {
@@ -366,7 +368,7 @@ typedef struct {
     int32_t waves_per_block;
     int32_t blocks_per_cu;
     int32_t reg_budget;
-    int32_t reserved;        /* must be 0           */
+    int32_t unroll;          /* 0, 1 or 2           */
 } sagms_plan;
 
 typedef struct {
@@ -379,7 +381,7 @@ typedef struct {
  * SAGMS_EUNSUPPORTED).  Checks every argument (SAGMS_EINVAL),
  * uploads the graphs' tables to the current device and synchronizes it.
  * The initial plan is SINGLE with tile_frames 8, waves_per_block 4,
- * blocks_per_cu 0 and reg_budget 0.  The batch keeps its own copy of cfg
+ * blocks_per_cu 0, reg_budget 0 and unroll 1.  The batch keeps its own copy of cfg
  * and of the segment table; the graphs must outlive it. */
 int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_decoder_cfg* cfg, sagms_batch* out);
 
@@ -401,10 +403,11 @@ int sagms_batch_instantiate(sagms_batch b);
 
 /* Autotuner: times every candidate plan (SINGLE, and TIERED when the codes
  * fall in more than one register class, with tile_frames in {4, 8, 16, 32},
- * waves_per_block in {1, 2, 4} and both register budgets where they differ;
- * PER_CODE with tile_frames in {4, 8, 16, 32}) on the batch's own
- * buffers, `reps` (1..100) timed runs each after one warm-up run, keeps the
- * plan with the smallest median time and returns it in *best (may be NULL).
+ * waves_per_block in {1, 2, 4}, unroll in {1, 2} and both register budgets
+ * where they differ; PER_CODE with tile_frames in {4, 8, 16, 32}) on the
+ * batch's own buffers, `reps` (1..100) timed runs each after one warm-up
+ * run, keeps the plan with the smallest median time and returns it in *best
+ * (may be NULL).
  * Up to `cap` results go to results (may be NULL), their number to *count
  * (may be NULL).  The runs overwrite the batch's outputs; the stream is
  * synchronized on return. */
@@ -417,7 +420,7 @@ int sagms_batch_destroy(sagms_batch b);
  * capture, tight serving loops, harnesses that forbid hipMalloc): one decode
  * of nseg (1..16) segments, as sagms_batch_create + sagms_batch_run with
  * `plan` (NULL = the initial plan of a batch: SINGLE, tile_frames 8,
- * waves_per_block 4), without a batch object.  Same checks and status codes
+ * waves_per_block 4, unroll 1), without a batch object.  Same checks and status codes
  * as sagms_batch_create and sagms_batch_set_plan; every frame's outputs equal
  * those of sagms_decode on that segment alone, bit for bit.
  *   Allocates nothing: no hipMalloc or hipFree, no host-to-device copy.  The

@@ -56,22 +56,23 @@ PLAN_KINDS = {"single": 0, "tiered": 1, "per_code": 2}
 
 class Plan(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("tile_frames", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("reg_budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("reg_budget", ctypes.c_int32), ("unroll", ctypes.c_int32)]
 
     def as_dict(self):
         kind = {v: k for k, v in PLAN_KINDS.items()}.get(self.kind, self.kind)
         return dict(kind=kind, tile_frames=self.tile_frames, waves_per_block=self.waves_per_block,
-                    blocks_per_cu=self.blocks_per_cu, reg_budget=self.reg_budget)
+                    blocks_per_cu=self.blocks_per_cu, reg_budget=self.reg_budget, unroll=self.unroll)
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("plan", Plan), ("ms", ctypes.c_float)]
 
 
-def plan(kind="single", tile_frames=8, waves_per_block=4, blocks_per_cu=0, reg_budget=0) -> Plan:
+def plan(kind="single", tile_frames=8, waves_per_block=4, blocks_per_cu=0, reg_budget=0, unroll=1) -> Plan:
     if kind not in PLAN_KINDS:
         raise ValueError("unknown plan kind %r" % kind)
-    return Plan(PLAN_KINDS[kind], int(tile_frames), int(waves_per_block), int(blocks_per_cu), int(reg_budget), 0)
+    return Plan(PLAN_KINDS[kind], int(tile_frames), int(waves_per_block), int(blocks_per_cu), int(reg_budget),
+                int(unroll))
 
 
 class GraphInfo(ctypes.Structure):

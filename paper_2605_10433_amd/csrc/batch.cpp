@@ -29,16 +29,18 @@ OccupancyCache::OccupancyCache() {
     for (auto& a : blocks)
         for (auto& b : a)
             for (auto& c : b)
-                for (int& d : c) d = -1;
+                for (auto& d : c)
+                    for (int& e : d) e = -1;
 }
 
-int OccupancyCache::get(int tier, int budget, int mt, int wpb, int* out) {
-    if (tier < 0 || tier >= kNumMixedTiers || budget < 0 || budget > 1 || mt < 0 || mt > 2 || wpb < 1 || wpb > 4)
+int OccupancyCache::get(int tier, int budget, int mt, int unroll, int wpb, int* out) {
+    if (tier < 0 || tier >= kNumMixedTiers || budget < 0 || budget > 1 || mt < 0 || mt > 2 || unroll < 1 ||
+        unroll > 2 || wpb < 1 || wpb > 4)
         return fail(SAGMS_EINVAL, "occupancy key out of range (internal)");
-    int& slot = blocks[tier][budget][mt][wpb];
+    int& slot = blocks[tier][budget][mt][unroll - 1][wpb];
     if (slot < 0) {
         int n = 0;
-        int rc = mixed_max_blocks(tier, budget, mt, wpb, &n);
+        int rc = mixed_max_blocks(tier, budget, mt, unroll, wpb, &n);
         if (rc) return rc;
         slot = n;
     }
@@ -68,13 +70,13 @@ int launch_segments(const MixedSegment* segs, int nseg, int tier, const MixedLau
     const int budget = mixed_budget_of(tier, p.reg_budget);
     const int wpb = mixed_waves_of(tier, p.waves_per_block);
     int per_cu = 0;
-    int rc = occ->get(tier, budget, mt, wpb, &per_cu);
+    int rc = occ->get(tier, budget, mt, p.unroll, wpb, &per_cu);
     if (rc) return rc;
     if (per_cu < 1) return fail(SAGMS_EUNSUPPORTED, "mixed kernel of tier %d does not fit a compute unit", tier);
     if (p.blocks_per_cu > 0) per_cu = std::min(per_cu, p.blocks_per_cu);
     int64_t blocks = (int64_t)per_cu * num_cu;
     blocks = std::min<int64_t>(blocks, (tiles + wpb - 1) / wpb);
-    return launch_mixed(tier, budget, mt, m, (int)blocks, wpb, st);
+    return launch_mixed(tier, budget, mt, p.unroll, m, (int)blocks, wpb, st);
 }
 
 int prepare_segments(const sagms_segment* segs, int nseg, const sagms_decoder_cfg* cfg, bool upload,
@@ -138,7 +140,7 @@ int check_plan(const sagms_plan* p) {
     if (!p) return fail(SAGMS_EINVAL, "plan is null");
     if (p->kind < SAGMS_PLAN_SINGLE || p->kind > SAGMS_PLAN_PER_CODE) return fail(SAGMS_EINVAL, "unknown plan kind %d", p->kind);
     if (p->tile_frames < 1 || p->tile_frames > 1024) return fail(SAGMS_EINVAL, "tile_frames must lie in [1, 1024]");
-    if (p->reserved != 0) return fail(SAGMS_EINVAL, "reserved field must be 0");
+    if (p->unroll < 0 || p->unroll > 2) return fail(SAGMS_EINVAL, "unroll must be 0, 1 or 2");
     if (p->kind == SAGMS_PLAN_PER_CODE) return SAGMS_OK;
     if (p->waves_per_block != 1 && p->waves_per_block != 2 && p->waves_per_block != 4)
         return fail(SAGMS_EINVAL, "waves_per_block must be 1, 2 or 4");
@@ -159,7 +161,7 @@ int enqueue_segments(const SegmentSet& set, const sagms_plan& p, int mt, int num
         }
         return SAGMS_OK;
     }
-    const MixedLaunch L{p.tile_frames, p.waves_per_block, p.blocks_per_cu, p.reg_budget};
+    const MixedLaunch L{p.tile_frames, p.waves_per_block, p.blocks_per_cu, p.reg_budget, p.unroll == 2 ? 2 : 1};
     // SINGLE: one launch with the largest tier's kernel; TIERED: one per tier
     for (int s0 = 0; s0 < set.nseg;) {
         int s1 = s0;
@@ -202,7 +204,7 @@ void drop_graph(Batch* b) {
 int blocks_per_cu(Batch* b, int tier, int* out) {
     const int budget = mixed_budget_of(tier, b->plan.reg_budget);
     const int wpb = mixed_waves_of(tier, b->plan.waves_per_block);
-    return b->occupancy.get(tier, budget, b->mt, wpb, out);
+    return b->occupancy.get(tier, budget, b->mt, b->plan.unroll == 2 ? 2 : 1, wpb, out);
 }
 
 int enqueue(Batch* b, hipStream_t st) {
@@ -237,7 +239,7 @@ int sagms_batch_create(const sagms_segment* segs, int32_t nseg, const sagms_deco
     }
     b->cfg = *cfg;
     b->mt = cfg->msg_precision;
-    b->plan = sagms_plan{SAGMS_PLAN_SINGLE, kMixedTileFrames, 4, 0, 0, 0};
+    b->plan = sagms_plan{SAGMS_PLAN_SINGLE, kMixedTileFrames, 4, 0, 0, 1};
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e == hipSuccess) e = hipMalloc(&b->d_queues, sizeof(uint32_t) * kScratchWords);
@@ -341,20 +343,22 @@ int sagms_batch_tune(sagms_batch bh, void* stream, int32_t reps, sagms_tune_resu
         for (int budget : {0, 1}) {
             if (budget == 1 && (kind == SAGMS_PLAN_SINGLE ? !mixed_has_budget(tiers[0], 1) : !tight))
                 continue;
-            for (int wpb : {1, 2, 4})
-                for (int tf : tiles) {
-                    // a waves-per-block value that every launched tier halves is a duplicate
-                    bool dup = true;
-                    for (int i = 0; i < nseg; ++i)
-                        if ((kind == SAGMS_PLAN_TIERED || tiers[i] == tiers[0]) && mixed_waves_of(tiers[i], wpb) == wpb)
-                            dup = false;
-                    if (dup) continue;
-                    sagms_plan p{kind, tf, wpb, 0, budget, 0};
-                    if (check_plan(&p) == SAGMS_OK) cands.push_back(p);
-                }
+            for (int unroll : {1, 2})
+                for (int wpb : {1, 2, 4})
+                    for (int tf : tiles) {
+                        // a waves-per-block value that every launched tier halves is a duplicate
+                        bool dup = true;
+                        for (int i = 0; i < nseg; ++i)
+                            if ((kind == SAGMS_PLAN_TIERED || tiers[i] == tiers[0]) &&
+                                mixed_waves_of(tiers[i], wpb) == wpb)
+                                dup = false;
+                        if (dup) continue;
+                        sagms_plan p{kind, tf, wpb, 0, budget, unroll};
+                        if (check_plan(&p) == SAGMS_OK) cands.push_back(p);
+                    }
         }
     }
-    for (int tf : tiles) cands.push_back(sagms_plan{SAGMS_PLAN_PER_CODE, tf, 4, 0, 0, 0});
+    for (int tf : tiles) cands.push_back(sagms_plan{SAGMS_PLAN_PER_CODE, tf, 4, 0, 0, 1});
     const sagms_plan saved = b->plan;
     hipGraphExec_t saved_exec = b->exec;
     hipGraph_t saved_graph = b->graph;
@@ -403,7 +407,7 @@ int sagms_batch_tune(sagms_batch bh, void* stream, int32_t reps, sagms_tune_resu
     b->graph = saved_graph;
     if (best_plan.kind != saved.kind || best_plan.tile_frames != saved.tile_frames ||
         best_plan.waves_per_block != saved.waves_per_block || best_plan.blocks_per_cu != saved.blocks_per_cu ||
-        best_plan.reg_budget != saved.reg_budget)
+        best_plan.reg_budget != saved.reg_budget || best_plan.unroll != saved.unroll)
         drop_graph(b);
     b->plan = best_plan;
     if (count) *count = std::min(n, cap);
@@ -416,7 +420,7 @@ int sagms_decode_segments(const sagms_segment* segs, int32_t nseg, const sagms_d
     SegmentSet set;
     int rc = prepare_segments(segs, nseg, cfg, false, &set);
     if (rc) return rc;
-    const sagms_plan p = plan ? *plan : sagms_plan{SAGMS_PLAN_SINGLE, kMixedTileFrames, 4, 0, 0, 0};
+    const sagms_plan p = plan ? *plan : sagms_plan{SAGMS_PLAN_SINGLE, kMixedTileFrames, 4, 0, 0, 1};
     rc = check_plan(&p);
     if (rc) return rc;
     uint32_t* queues = nullptr;

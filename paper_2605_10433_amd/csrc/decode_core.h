@@ -277,8 +277,12 @@ struct WaveDecoder {
     // Decodes frame f, whose syndrome bits are sb, and writes its outputs.
     // The syndrome of frame f_next is loaded when the frame starts and left
     // in sb when its rounds are done, so the load latency hides behind them.
+    // UR: rounds per iteration of the round loop (1 or 2; each round keeps
+    // its own exit tests, so the results do not depend on it).
+    template <int UR = 1>
     __device__ __forceinline__ void frame(const DecodeArgs& a, float* lds, int lane, int64_t f, uint32_t (&sb)[CPL],
                                           int64_t f_next, const KernelGains* kg = nullptr) {
+        static_assert(UR == 1 || UR == 2, "one or two rounds per loop iteration");
         uint64_t next_word[CPL];
         load_syndrome(a, f_next, next_word);
         float post[VPL];
@@ -296,7 +300,8 @@ struct WaveDecoder {
 
         int it = 0;
         bool conv = false;
-        while (true) {
+        // one round; false once the frame is done
+        auto round = [&]() -> bool {
             // top of the round: v2c, hard-decision parity, residual syndrome
             float v[CPL][DC];
             bool unsat[CPL];  // residual syndrome bit: s xor (H e_hat) of the check
@@ -314,9 +319,9 @@ struct WaveDecoder {
             }
             if (w == 0) {
                 conv = true;
-                break;
+                return false;
             }
-            if (it == a.lmax) break;
+            if (it == a.lmax) return false;
             ++it;
             // CN update; gains of the residual weight w (eq. (alphaeff))
             float2 gg;
@@ -342,6 +347,11 @@ struct WaveDecoder {
                 lds[LY::POST0 + k * 64 + lane] = s;
             }
             wave_lds_sync();
+            return true;
+        };
+        while (round()) {
+            if constexpr (UR == 2)
+                if (!round()) break;
         }
 
         syndrome_bits(a, lane, next_word, sb);

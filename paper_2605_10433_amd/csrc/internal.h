@@ -285,10 +285,11 @@ int mixed_words(int tier);
 // compiler's allocation, 1 = one more resident wave per SIMD).
 bool mixed_has_budget(int tier, int budget);
 // Resident blocks per CU of a mixed kernel (occupancy of registers and LDS).
-int mixed_max_blocks(int tier, int budget, int mt, int waves_per_block, int* out);
+int mixed_max_blocks(int tier, int budget, int mt, int unroll, int waves_per_block, int* out);
 // Zeroes the queue counters, then launches the persistent kernel (MS / SMS /
 // SAGMS; BP has no mixed kernel).
-int launch_mixed(int tier, int budget, int mt, const MixedArgs& m, int blocks, int waves_per_block, hipStream_t st);
+int launch_mixed(int tier, int budget, int mt, int unroll, const MixedArgs& m, int blocks, int waves_per_block,
+                 hipStream_t st);
 
 // Register class of a shape index (-1 if none).
 int mixed_tier_of_shape(int shape_idx);
@@ -302,13 +303,13 @@ int mixed_waves_of(int tier, int requested);
 // register budget, message format, waves per block); a fixed table, so that
 // lookups never allocate.
 struct OccupancyCache {
-    int blocks[kNumMixedTiers][2][3][5];
+    int blocks[kNumMixedTiers][2][3][2][5];  // [tier][budget][format][unroll - 1][waves per block]
     OccupancyCache();
-    int get(int tier, int budget, int mt, int waves_per_block, int* out);
+    int get(int tier, int budget, int mt, int unroll, int waves_per_block, int* out);
 };
 
 struct MixedLaunch {
-    int tile_frames, waves_per_block, blocks_per_cu, reg_budget;
+    int tile_frames, waves_per_block, blocks_per_cu, reg_budget, unroll;
 };
 
 // One persistent launch over nseg segments (all of register class <= tier)

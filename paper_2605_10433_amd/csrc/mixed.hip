@@ -82,7 +82,8 @@ __device__ __forceinline__ int segment_of(const MixedArgs& m, int64_t t) {
 
 // Decodes tile t of segment s and every following tile the wave draws from
 // the same segment; returns the first tile of another segment (or -1).
-template <int DC, int DV, int CPL, int VPL, bool BP, int MT>
+// UR: rounds per iteration of the round loop.
+template <int DC, int DV, int CPL, int VPL, bool BP, int MT, int UR>
 __device__ __forceinline__ int64_t run_segment(const MixedArgs& m, int s, int64_t t, TileQueue& q, float* lds,
                                                int lane) {
     const DecodeArgs a = m.segs[s].a;  // private copy: the output stores cannot alias it
@@ -97,15 +98,16 @@ __device__ __forceinline__ int64_t run_segment(const MixedArgs& m, int s, int64_
         uint32_t sb[CPL];
         WD::load_syndrome(a, f0, word);
         WD::syndrome_bits(a, lane, word, sb);
-        for (int64_t f = f0; f < f1; ++f) d.frame(a, lds, lane, f, sb, f + 1 < f1 ? f + 1 : f);
+        for (int64_t f = f0; f < f1; ++f) d.template frame<UR>(a, lds, lane, f, sb, f + 1 < f1 ? f + 1 : f);
         t = q.next(m, lane);
     } while (t >= tb && t < te);
     return t;
 }
 
 // HI: highest shape index compiled in (the tier); WPE: waves per SIMD the
-// register allocator must allow (1 = no constraint beyond the hardware's).
-template <int HI, int WPE, int MT>
+// register allocator must allow (1 = no constraint beyond the hardware's);
+// UR: decoding rounds per iteration of the round loop (1 or 2).
+template <int HI, int WPE, int MT, int UR>
 __global__ void __launch_bounds__(64 * kMixedMaxWavesPerBlock) __attribute__((amdgpu_waves_per_eu(WPE)))
 mixed_kernel(MixedArgs m) {
     extern __shared__ float lds_all[];
@@ -119,7 +121,7 @@ mixed_kernel(MixedArgs m) {
         switch (m.segs[s].shape) {
 #define MIXED_CASE(I, DC, DV, CPL, VPL)                                                 \
     case I:                                                                            \
-        if constexpr (I <= HI) t = run_segment<DC, DV, CPL, VPL, false, MT>(m, s, t, q, lds, lane); \
+        if constexpr (I <= HI) t = run_segment<DC, DV, CPL, VPL, false, MT, UR>(m, s, t, q, lds, lane); \
         else t = -1;                                                                   \
         break;
             SAGMS_DECODE_SHAPES(MIXED_CASE)
@@ -157,37 +159,45 @@ int mixed_words(int tier) {
 
 using MixedFn = void (*)(MixedArgs);
 
+template <int HI, int WPE, int UR>
+static MixedFn pick_format(int mt) {
+    if (mt == SAGMS_MSG_FP16) return mixed_kernel<HI, WPE, SAGMS_MSG_FP16, UR>;
+    if (mt == SAGMS_MSG_INT6) return mixed_kernel<HI, WPE, SAGMS_MSG_INT6, UR>;
+    return mixed_kernel<HI, WPE, SAGMS_MSG_FP32, UR>;
+}
+
 template <int HI, int WPE>
-static MixedFn pick_kernel(int mt) {
-    if (mt == SAGMS_MSG_FP16) return mixed_kernel<HI, WPE, SAGMS_MSG_FP16>;
-    if (mt == SAGMS_MSG_INT6) return mixed_kernel<HI, WPE, SAGMS_MSG_INT6>;
-    return mixed_kernel<HI, WPE, SAGMS_MSG_FP32>;
+static MixedFn pick_kernel(int mt, int unroll) {
+    return unroll == 2 ? pick_format<HI, WPE, 2>(mt) : pick_format<HI, WPE, 1>(mt);
 }
 
 // Register budgets: 0 = the compiler's allocation; 1 = a tighter budget that
 // buys one more resident wave per SIMD (tiers 1 and 2 only; it may spill).
-static MixedFn mixed_fn(int tier, int budget, int mt) {
+// Unroll: 1 or 2 rounds per iteration of the round loop.
+static MixedFn mixed_fn(int tier, int budget, int mt, int unroll) {
+    if (unroll != 1 && unroll != 2) return nullptr;
     if (budget == 0) {
         switch (tier) {
-            case 0: return pick_kernel<kMixedTiers[0], 1>(mt);
-            case 1: return pick_kernel<kMixedTiers[1], 1>(mt);
-            case 2: return pick_kernel<kMixedTiers[2], 1>(mt);
-            case 3: return pick_kernel<kMixedTiers[3], 1>(mt);
+            case 0: return pick_kernel<kMixedTiers[0], 1>(mt, unroll);
+            case 1: return pick_kernel<kMixedTiers[1], 1>(mt, unroll);
+            case 2: return pick_kernel<kMixedTiers[2], 1>(mt, unroll);
+            case 3: return pick_kernel<kMixedTiers[3], 1>(mt, unroll);
         }
     } else if (budget == 1) {
         switch (tier) {
-            case 1: return pick_kernel<kMixedTiers[1], 5>(mt);
-            case 2: return pick_kernel<kMixedTiers[2], 3>(mt);
+            case 1: return pick_kernel<kMixedTiers[1], 5>(mt, unroll);
+            case 2: return pick_kernel<kMixedTiers[2], 3>(mt, unroll);
         }
     }
     return nullptr;
 }
 
-bool mixed_has_budget(int tier, int budget) { return mixed_fn(tier, budget, SAGMS_MSG_FP32) != nullptr; }
+bool mixed_has_budget(int tier, int budget) { return mixed_fn(tier, budget, SAGMS_MSG_FP32, 1) != nullptr; }
 
-int mixed_max_blocks(int tier, int budget, int mt, int waves_per_block, int* out) {
-    MixedFn fn = mixed_fn(tier, budget, mt);
-    if (!fn) return fail(SAGMS_EINVAL, "no mixed kernel for tier %d, register budget %d", tier, budget);
+int mixed_max_blocks(int tier, int budget, int mt, int unroll, int waves_per_block, int* out) {
+    MixedFn fn = mixed_fn(tier, budget, mt, unroll);
+    if (!fn)
+        return fail(SAGMS_EINVAL, "no mixed kernel for tier %d, register budget %d, unroll %d", tier, budget, unroll);
     if (waves_per_block < 1 || waves_per_block > kMixedMaxWavesPerBlock)
         return fail(SAGMS_EINVAL, "waves_per_block must lie in [1, %d]", kMixedMaxWavesPerBlock);
     const size_t lds = (size_t)waves_per_block * mixed_words(tier) * sizeof(float);
@@ -198,10 +208,11 @@ int mixed_max_blocks(int tier, int budget, int mt, int waves_per_block, int* out
     return SAGMS_OK;
 }
 
-int launch_mixed(int tier, int budget, int mt, const MixedArgs& m, int blocks, int waves_per_block,
+int launch_mixed(int tier, int budget, int mt, int unroll, const MixedArgs& m, int blocks, int waves_per_block,
                  hipStream_t st) {
-    MixedFn fn = mixed_fn(tier, budget, mt);
-    if (!fn) return fail(SAGMS_EINVAL, "no mixed kernel for tier %d, register budget %d", tier, budget);
+    MixedFn fn = mixed_fn(tier, budget, mt, unroll);
+    if (!fn)
+        return fail(SAGMS_EINVAL, "no mixed kernel for tier %d, register budget %d, unroll %d", tier, budget, unroll);
     if (m.nq < 1 || m.nq > kMaxQueues || m.nseg < 1 || m.nseg > kMaxSegments || m.tile_frames < 1 ||
         m.words != mixed_words(tier) || blocks < 1 || waves_per_block < 1 ||
         waves_per_block > kMixedMaxWavesPerBlock)

@@ -180,7 +180,7 @@ int launch(Server* s, Slot& x, int tier, double t) {
         ms.push_back(m);
     }
     SAGMS_HIP(hipMemcpyAsync(x.d_in, x.h_in, (size_t)in_w * 8, hipMemcpyHostToDevice, x.st));
-    MixedLaunch L{s->scfg.tile_frames, s->scfg.waves_per_block, 0, s->scfg.reg_budget};
+    MixedLaunch L{s->scfg.tile_frames, s->scfg.waves_per_block, 0, s->scfg.reg_budget, 1};
     int rc = launch_segments(ms.data(), (int)ms.size(), tier, L, s->num_cu, s->mt, x.d_queues, &s->occ, x.st);
     if (rc) return rc;
     SAGMS_HIP(hipMemcpyAsync(x.h_out, x.d_out, (size_t)off, hipMemcpyDeviceToHost, x.st));

@@ -273,8 +273,10 @@ def test_batch_create_checks_before_device_work():
 
 
 def test_plan_structures():
-    p = sagms.plan("tiered", tile_frames=16, waves_per_block=2, blocks_per_cu=3, reg_budget=1)
-    assert p.as_dict() == dict(kind="tiered", tile_frames=16, waves_per_block=2, blocks_per_cu=3, reg_budget=1)
+    p = sagms.plan("tiered", tile_frames=16, waves_per_block=2, blocks_per_cu=3, reg_budget=1, unroll=2)
+    assert p.as_dict() == dict(kind="tiered", tile_frames=16, waves_per_block=2, blocks_per_cu=3, reg_budget=1,
+                               unroll=2)
+    assert sagms.plan().unroll == 1
     assert ctypes.sizeof(sagms.Plan) == 24 and ctypes.sizeof(sagms.Segment) == 64
     with pytest.raises(ValueError):
         sagms.plan("bogus")

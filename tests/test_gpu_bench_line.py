@@ -3,7 +3,8 @@ steps of the l = 63 workload) prints one JSON line with the fields its
 readers rely on: the metric and its unit, the timed steps, one GPU, the
 configuration, the roofline object of the decode kernel (with the survey's
 14-operation fraction), the FP16 pass over the same frames and the serving
-latency at 80 % load."""
+latency at 80 % load.  The mixed-code workload's line, after the plan
+autotuner, names the tuned plan and the tuner's log."""
 import json
 import os
 import subprocess
@@ -49,3 +50,27 @@ def test_bench_prints_one_complete_line():
     assert 0 <= f16["fer"] <= 1 and isinstance(f16["fer_in_fp32_interval"], bool)
     srv = out["serving_p80"]
     assert 0 < srv["p50_us"] <= srv["p99_us"] and srv["offered_load"] == 0.8 and srv["requests"] > 0
+
+
+def test_mix_workload_line_with_tuner():
+    """bench.py --workload mix --tune: one line naming the tuned plan (with
+    its unroll), the tuner's log and the per-code FER of the mixed batch."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("bench line: mix, tuned, 2 steps", flush=True)
+    r = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--workload", "mix", "--tune",
+                        "--steps", "2", "--warmup", "1", "--no-cpu-baseline"],
+                       capture_output=True, text=True, timeout=240, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    assert out["value"] > 0 and out["steps"] == 2 and out["config"]["tuned"] is True
+    plan = out["config"]["plan"]
+    assert plan["unroll"] in (1, 2)
+    best = min(out["tune"], key=lambda t: t["ms"])
+    assert best["plan"] == plan
+    assert {t["plan"]["unroll"] for t in out["tune"] if t["plan"]["kind"] != "per_code"} == {1, 2}
+    assert set(out["per_code"]) == set(out["config"]["codes"])
+    for rec in out["per_code"].values():
+        assert 0 <= rec["fer"] <= 1 and rec["mean_iters"] > 0

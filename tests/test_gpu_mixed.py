@@ -96,10 +96,11 @@ def mix_segments(dev, p=0.04, mix=MIX, soft=True):
     return [make_segment(name, nf, p, workloads.mix_stream(i, p), dev, soft=soft) for i, (name, nf) in enumerate(mix)]
 
 
-PLANS = [dict(kind="single", tile_frames=t, waves_per_block=w, reg_budget=r)
-         for t, w, r in ((1, 4, 0), (7, 4, 0), (32, 1, 0), (8, 2, 1), (3, 4, 1))] + \
+PLANS = [dict(kind="single", tile_frames=t, waves_per_block=w, reg_budget=r, unroll=u)
+         for t, w, r, u in ((1, 4, 0, 1), (7, 4, 0, 2), (32, 1, 0, 1), (8, 2, 1, 2), (3, 4, 1, 1), (5, 1, 1, 2))] + \
         [dict(kind="tiered", tile_frames=5, waves_per_block=2), dict(kind="tiered", tile_frames=16, reg_budget=1),
-         dict(kind="per_code", tile_frames=3), dict(kind="single", tile_frames=4, blocks_per_cu=1)]
+         dict(kind="tiered", tile_frames=2, reg_budget=1, unroll=2), dict(kind="per_code", tile_frames=3),
+         dict(kind="single", tile_frames=4, blocks_per_cu=1), dict(kind="single", tile_frames=6, unroll=0)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "int6"])
@@ -201,6 +202,7 @@ def test_autotuner_returns_a_valid_plan(dev):
     best, results = batch.tune(reps=1)
     say("tuned", best.as_dict(), len(results))
     assert len(results) >= 10
+    assert {pl["unroll"] for pl, _ in results if pl["kind"] != "per_code"} == {1, 2}
     assert best.as_dict() == batch.get_plan().as_dict()
     assert min(ms for _, ms in results) == pytest.approx(
         [ms for pl, ms in results if pl == best.as_dict()][0])
@@ -241,7 +243,7 @@ def test_plan_and_argument_checks(dev):
     cfg = sagms.decoder_config("sagms")
     batch = sagms.Batch(segs, cfg)
     for bad in (dict(tile_frames=0), dict(tile_frames=2000), dict(waves_per_block=3), dict(blocks_per_cu=-1),
-                dict(reg_budget=2)):
+                dict(reg_budget=2), dict(unroll=3), dict(unroll=-1)):
         with pytest.raises(sagms.SagmsError) as e:
             batch.set_plan(sagms.plan(**bad))
         assert e.value.code == sagms.EINVAL

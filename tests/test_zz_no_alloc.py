@@ -57,8 +57,8 @@ def clobber(segs):
         s["posterior"].fill_(float("nan"))
 
 
-PLANS = [None, sagms.plan("single", tile_frames=4, waves_per_block=2), sagms.plan("tiered", tile_frames=16),
-         sagms.plan("per_code", tile_frames=8)]
+PLANS = [None, sagms.plan("single", tile_frames=4, waves_per_block=2),
+         sagms.plan("tiered", tile_frames=16, unroll=2), sagms.plan("per_code", tile_frames=8)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
