@@ -65,7 +65,10 @@ typedef enum {
  *             - its own previous output (FP32), computes its output by the
  *             same check rule and gains as FLOODING, and sets posterior =
  *             v2c + new output, so later layers see earlier layers' updates
- *             within the round.  Gains, hard decisions, the residual test
+ *             within the round (the kernel may run checks of several
+ *             layers in one pass when every variable still meets its checks
+ *             in layer order, which gives the same results).  Gains, hard
+ *             decisions, the residual test
  *             and the round count are as in FLOODING (gains from the
  *             residual syndrome at the start of the round).  MS, SMS and
  *             SAGMS with FP32 messages, sagms_decode / sagms_decode_soft
@@ -134,6 +137,9 @@ typedef struct {
     int32_t joint;         /* 1 for a joint graph (sagms_build_gb_joint)      */
     int32_t words_e;       /* words per estimate frame: words_n, or 2 words_n
                               (x part, then z part) for a joint graph         */
+    int32_t layered_group; /* SAGMS_LAYERED: lanes per frame (4 .. 64), or 0
+                              when the layered schedule cannot run the graph */
+    int32_t layered_passes;/* SAGMS_LAYERED: passes per round (0 likewise)    */
 } sagms_graph_info_t;
 
 /* ---- graphs (host only; no device needed) ----------------------------- */

@@ -77,7 +77,8 @@ def plan(kind="single", tile_frames=8, waves_per_block=4, blocks_per_cu=0, reg_b
 
 class GraphInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
-                ("m", "n", "n_edges", "k", "dc_max", "dv_max", "words_n", "words_m", "joint", "words_e")]
+                ("m", "n", "n_edges", "k", "dc_max", "dv_max", "words_n", "words_m", "joint", "words_e",
+                 "layered_group", "layered_passes")]
 
 
 def lib():

@@ -640,6 +640,9 @@ int sagms_graph_info(sagms_graph gh, sagms_graph_info_t* info) {
     info->words_m = g->wm;
     info->joint = g->joint ? 1 : 0;
     info->words_e = g->we;
+    const bool layered = g->layered.status == SAGMS_OK;
+    info->layered_group = layered ? g->layered.group : 0;
+    info->layered_passes = layered ? g->layered.passes : 0;
     return SAGMS_OK;
 }
 

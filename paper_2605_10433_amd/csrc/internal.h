@@ -116,8 +116,10 @@ struct GainLaw {
 // the posteriors (npad words), each check's outputs in compressed form (4
 // words per check) and the syndrome and residual bits (2 * wm words each).
 // Schedules of at most this many passes keep each lane's check outputs in
-// registers (layered.hip); longer ones keep them in LDS.
-constexpr int kLayeredRegPasses = 16;
+// registers (layered.hip; a second, shorter register form serves schedules
+// of at most kLayeredRegPassesShort passes); longer ones keep them in LDS.
+constexpr int kLayeredRegPasses = 24;
+constexpr int kLayeredRegPassesShort = 16;
 
 // Host part of the layered plan, computed when the graph is built; status
 // is SAGMS_OK when the layered schedule can run the graph, else the code

@@ -3,15 +3,19 @@
 // implemented here is stated with SAGMS_LAYERED in sagms.h).
 //
 // The host splits the checks into layers of checks with pairwise disjoint
-// supports (first fit in ascending check index) and every layer into passes
-// of at most G checks.  A wavefront decodes F = 64 / G frames at once, one
-// per group of G lanes.  In pass p, lane q of a group updates check
-// pass_check[p][q] of its frame: it reads its variables' posteriors and its
-// own previous outputs from LDS, forms v2c = posterior - c2v_old, computes
-// the check output with the operations of the flooding decoder's check
-// update, and writes c2v_new and posterior = v2c + c2v_new back.  The checks
-// of one pass touch disjoint variables, and one wavefront's LDS operations
-// complete in order, so the passes need no barrier.
+// supports (first fit in ascending check index) and packs them into passes
+// of at most G checks: in (layer, position) order, each check goes to the
+// earliest pass after every pass that holds a check sharing a variable with
+// it.  Each variable therefore meets its checks in layer order, and every
+// check reads the posteriors the layer-by-layer schedule would give it.  A
+// wavefront decodes F = 64 / G frames at once, one per group of G lanes.  In
+// pass p, lane q of a group updates check pass_check[p][q] of its frame: it
+// reads its variables' posteriors and its own previous outputs, forms
+// v2c = posterior - c2v_old, computes the check output with the operations
+// of the flooding decoder's check update, and writes c2v_new and
+// posterior = v2c + c2v_new back.  The checks of one pass touch disjoint
+// variables, and one wavefront's LDS operations complete in order, so the
+// passes need no barrier.
 //
 // A check's DC outputs are kept in three words instead of DC: S1 (the
 // output magnitude of the non-minimum edges with the parity sign), S1 xor S2
@@ -62,10 +66,12 @@ __device__ __forceinline__ uint64_t group_segment(uint64_t ballot, int grp) {
 }
 
 // PMAX = 0: check outputs in LDS; PMAX > 0: in registers, at most PMAX passes
-// (register budget: 4 wavefronts per SIMD, 3 for degree 10, whose 16 passes
-// of outputs and wider check update do not fit 128 VGPRs).
+// (register budget: 4 wavefronts per SIMD for up to 16 passes of degree 6 or
+// 8, else 3: the outputs of more passes, or the wider check update of degree
+// 10, do not fit the 128 VGPRs of a fourth).
 template <int DC, int G, int PMAX>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PMAX > 0 ? (DC >= 10 ? 3 : 4) : 1)))
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(PMAX > 0 ? (DC >= 10 || PMAX > kLayeredRegPassesShort ? 3 : 4) : 1)))
 layered_kernel(LayeredArgs la) {
     constexpr int F = 64 / G;
     static_assert(F * G == 64, "G must divide 64");
@@ -170,6 +176,7 @@ layered_kernel(LayeredArgs la) {
                     reinterpret_cast<uint8_t*>(rbits)[2 * r] = (uint8_t)seg;
                     reinterpret_cast<uint8_t*>(rbits)[2 * r + 1] = (uint8_t)(seg >> 8);
                 } else {
+                    static_assert(G == 8, "group sizes 8, 16, 32, 64");
                     reinterpret_cast<uint8_t*>(rbits)[r] = (uint8_t)seg;
                 }
             }
@@ -381,7 +388,11 @@ int launch_dp(int G, const LayeredArgs& la, size_t lds, int num_cu, hipStream_t 
 
 template <int DC>
 int launch_d(int G, bool regs, const LayeredArgs& la, size_t lds, int num_cu, hipStream_t st) {
-    return regs ? launch_dp<DC, kLayeredRegPasses>(G, la, lds, num_cu, st) : launch_dp<DC, 0>(G, la, lds, num_cu, st);
+    if (!regs) return launch_dp<DC, 0>(G, la, lds, num_cu, st);
+    // the shorter register form where it holds the schedule: fewer registers
+    // to clear when a frame starts, and a fourth wavefront for degrees 6, 8
+    if (la.P <= kLayeredRegPassesShort) return launch_dp<DC, kLayeredRegPassesShort>(G, la, lds, num_cu, st);
+    return launch_dp<DC, kLayeredRegPasses>(G, la, lds, num_cu, st);
 }
 
 }  // namespace

@@ -396,3 +396,45 @@ def test_codes_beyond_every_decode_shape_are_refused():
         assert "no decode kernel" in sagms.lib().sagms_last_error().decode()
         assert _create_rc(_segments([g], [4]), 1, sagms.decoder_config("sagms")) == sagms.EUNSUPPORTED
     assert (big.n, big.dc_max) == (1200, 10) and wide.dc_max == 20
+
+
+def _packed_passes(h, group):
+    """Passes of the layered schedule with `group` lanes: the checks of the
+    first-fit layers in (layer, position) order, each in the earliest pass
+    after every pass holding a check that shares a variable with it and with
+    a free lane (so every variable meets its checks in layer order)."""
+    from oracle import layered
+    last = np.full(h.shape[1], -1)
+    fill = []
+    for layer in layered.greedy_layers(h):
+        for c in layer:
+            vs = np.nonzero(h[c])[0]
+            p = int(last[vs].max()) + 1
+            while p < len(fill) and fill[p] == group:
+                p += 1
+            if p == len(fill):
+                fill.append(0)
+            fill[p] += 1
+            last[vs] = p
+    return len(fill)
+
+
+@pytest.mark.parametrize("name", ["G63", "G127", "G255w3", "G255w4", "G511w5"])
+def test_layered_plan_packs_passes(name):
+    """The layered plan's pass count is that of the packing for its group
+    size, never more than one pass per layer slice would take, and the group
+    holds the syndrome and estimate words; l = 511 (weight 5): 21 passes of
+    32 lanes where one pass per layer takes 18 passes of 64 (672 against
+    1152 lane slots per frame and round)."""
+    from oracle import layered
+    l, a, b = workloads.code(name)
+    _, hz = codes.gb_matrices(l, a, b)
+    g = sagms.Graph.gb(l, a, b)
+    G, P = g.layered_group, g.layered_passes
+    assert G in (8, 16, 32, 64) and G >= max(g.words_m, g.words_n)
+    assert P == _packed_passes(hz, G)
+    assert P <= sum(-(-len(layer) // G) for layer in layered.greedy_layers(hz))
+    if name == "G63":
+        assert (G, P) == (8, 14)   # 14 layers of at most 6 checks form a chain: nothing to pack
+    if name == "G511w5":
+        assert (G, P) == (32, 21)

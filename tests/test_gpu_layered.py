@@ -94,9 +94,10 @@ def test_layered_arbitrary_inputs(dev, lmax, kind, kw):
     check_against_oracle("G63", kind, kw, s, llr, lmax, dev)
 
 
-@pytest.mark.parametrize("nf", [0, 1, 2, 7, 8, 9, 63, 65])
-def test_layered_small_batches(dev, nf):
-    l, a, b = workloads.code("G127")
+@pytest.mark.parametrize("nf", [0, 1, 2, 7, 8, 9, 15, 16, 17, 63, 65])
+@pytest.mark.parametrize("name", ["G127", "G63"])
+def test_layered_small_batches(dev, name, nf):
+    l, a, b = workloads.code(name)
     hz = codes.gb_matrices(l, a, b)[1]
     ex, _ = channel.sample_paulis(5, 1, 0, max(nf, 1), 2 * l, 0.05)
     s = channel.syndrome(hz, ex)[:nf]
@@ -106,7 +107,7 @@ def test_layered_small_batches(dev, nf):
                                       sagms.decoder_config("sagms", schedule="layered"), dev)
         assert it.size == 0
         return
-    check_against_oracle("G127", "sagms", dict(workloads.SAGMS_PARAMS), s,
+    check_against_oracle(name, "sagms", dict(workloads.SAGMS_PARAMS), s,
                          np.full(2 * l, channel.prior_llr(0.05), np.float32), 100, dev)
 
 
@@ -149,9 +150,10 @@ def test_layered_full_size(dev):
 
 
 def test_layered_layer_wider_than_a_wavefront(dev):
-    """80 checks with disjoint supports (one layer, cut into passes of 64 and
-    16 checks) plus 10 checks across them (further layers), degree 6,
-    n = 480: against the oracle's layered FP32 mode."""
+    """80 checks with disjoint supports (one layer, wider than a wavefront,
+    so it spans several passes whatever the group size) plus 10 checks
+    across them (further layers), degree 6, n = 480: against the oracle's
+    layered FP32 mode."""
     rng = np.random.default_rng(21)
     m0, n = 80, 480
     h = np.zeros((m0 + 10, n), dtype=np.uint8)
@@ -164,6 +166,7 @@ def test_layered_layer_wider_than_a_wavefront(dev):
     lay = layered.greedy_layers(h)
     assert len(lay[0]) > 64 and len(lay) > 1
     g = sagms.Graph.from_dense(h)
+    assert g.layered_passes * g.layered_group >= m0 + 10 and g.layered_passes > 1
     s = rng.integers(0, 2, (96, h.shape[0])).astype(np.uint8)
     llr = rng.uniform(1.0, 4.0, n).astype(np.float32)
     for kind, kw in KINDS:
