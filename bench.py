@@ -80,6 +80,9 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "decode_g63_sagms_p005_counters.j
 OPS_PER_EDGE_UPDATE_SURVEY = 14
 
 
+DTYPES = {"fp32": "f32", "fp16": "f16 messages, f32 posteriors", "int6": "int6 messages"}
+
+
 def measured_counters(frames, p):
     """Counter-derived roofline fractions of the decode kernel from the
     committed record, or None."""
@@ -349,7 +352,7 @@ def run_mix(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f16 messages, f32 posteriors", "int6": "int6 messages"}[args.precision],
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {"workload": "mixed GB codes %s at %s %% of %d Philox frames/step, code-capacity depolarizing "
                                "p=%g, %s l_max=%d early exit, flooding, %s messages, one batch run per step"
@@ -502,7 +505,7 @@ def serve_measure(args, loads):
             "unit": "us (p99)",
             "higher_is_better": False,
             "n_gpus": 1,
-            "dtype": {"fp32": "f32", "fp16": "f16 messages, f32 posteriors", "int6": "int6 messages"}[args.precision],
+            "dtype": DTYPES[args.precision],
             "data": "synthetic",
             "p50_us": float(np.percentile(lat, 50)),
             "p99_us": float(np.percentile(lat, 99)),
@@ -647,7 +650,7 @@ def main():
                                                        buf["iters"], ctr, **kw)) if joint else \
         (lambda buf, ctr, **kw: sagms.judge(g, buf["ex"], buf["ehat"], buf["converged"], buf["iters"], ctr, **kw))
     cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, alpha=args.alpha, frames_per_wave=args.frames_per_wave,
-                               schedule=args.schedule, **workloads.SAGMS_PARAMS)
+                               schedule=args.schedule, precision=args.precision, **workloads.SAGMS_PARAMS)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
     # --pipeline: the sampler of step s + 1 runs on a second stream while step
@@ -748,7 +751,8 @@ def main():
     fer = c[0] / frames
     lo, hi = wilson(int(c[0]), frames)
     value = frames / (total_ms * 1e-3)
-    default_workload = args.graph == "gb" and args.decoder == "sagms" and args.schedule == "flooding"
+    default_workload = (args.graph == "gb" and args.decoder == "sagms" and args.schedule == "flooding"
+                        and args.precision == "fp32")
     extras = default_workload and not args.no_extras
     fp16 = serving = None
     if extras:
@@ -787,15 +791,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {"workload": ("GB l=63 [[126,28]] joint X/Z decoding (X- and Z-type rows: m=126, d_c=d_v=10, "
                                 "E=1260, scalar messages), code-capacity depolarizing eps=%g" if joint else
                                 "GB l=63 [[126,28]] (H_Z: m=63, d_c=10, d_v=5, E=630), code-capacity depolarizing "
-                                "p=%g") % p + ", %d Philox frames/step, %s l_max=%d early exit, %s, FP32 messages"
-                               % (nf, args.decoder.upper(), args.lmax, args.schedule),
+                                "p=%g") % p + ", %d Philox frames/step, %s l_max=%d early exit, %s, %s messages"
+                               % (nf, args.decoder.upper(), args.lmax, args.schedule, args.precision.upper()),
                    "code": "G63", "graph": args.graph, "frames_per_wave": args.frames_per_wave, "p": p, "frames_per_step": nf, "decoder": args.decoder, "lmax": args.lmax,
-                   "schedule": args.schedule, "pipeline": bool(args.pipeline)},
+                   "schedule": args.schedule, "precision": args.precision, "pipeline": bool(args.pipeline)},
         "edge_updates_per_s": edge_updates / (total_ms * 1e-3),
         "decode_ms_per_step": mean_dec_ms,
         "decode_frames_per_s": nf / (mean_dec_ms * 1e-3),
