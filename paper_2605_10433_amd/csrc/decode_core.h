@@ -142,8 +142,7 @@ __device__ __forceinline__ uint32_t or_and(uint32_t a, uint32_t b, uint32_t c) {
 // Message formats: FP32; FP16 (every message saturated to +-65504 and
 // rounded to half, posteriors FP32); INT6 (sign + 6-bit magnitude on a grid
 // of step 1/4, saturating at +-63 steps; the prior is quantized as well, so
-// posterior sums are exact).  FP32 and INT6 messages are held as FP32
-// values, FP16 messages as half bit patterns (see half_hi).
+// posterior sums are exact).  Messages are held as FP32 values.
 //
 // Only the check outputs are rounded.  Both roundings are monotone and keep
 // the sign, so the minimum, the second minimum and the sign parity of the
@@ -177,65 +176,27 @@ __device__ __forceinline__ float prior(float x) {
     }
 }
 
-// FP16 messages are held as IEEE half bit patterns.  A check output sits in
-// the high 16 bits of a 32-bit word, so its sign is bit 31 and the sign rule
-// of the FP32 path applies to it unchanged; LDS slots hold such words.  The
-// VN sum and v2c = posterior - c2v widen a half with v_fma_mix_f32, whose
-// product by +-1 is exact, so the one rounding is that of the FP32 add or
-// subtract of the widened value.  (Written out because the compiler turns
-// an fma by +-1 back into a conversion and an add.)
-__device__ __forceinline__ uint32_t half_hi(float x) {
-    const _Float16 h = (_Float16)__builtin_amdgcn_fmed3f(x, -65504.0f, 65504.0f);  // nearest even
-    return (uint32_t)__builtin_bit_cast(uint16_t, h) << 16;
-}
-// post - (the half in the low (HI = 0) or high (HI = 1) 16 bits of w)
-template <int HI>
-__device__ __forceinline__ float half_sub(uint32_t w, float post) {
-    float r;
-    if constexpr (HI)
-        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(post));
-    else
-        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(post));
-    return r;
-}
-// s + (the half in the high 16 bits of w)
-__device__ __forceinline__ float half_add_hi(uint32_t w, float s) {
-    float r;
-    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(s));
-    return r;
-}
-
 // Check-node update of one check (eq. (ms_cn) scaled per eq. (alphaeff) /
 // (sagms_cn), or eq. (bp4_cn) for BP): v = incoming v2c messages, sb = the
 // original syndrome bit at the sign position, unsat = the residual bit,
 // gs / gu = the gains of a satisfied / unsatisfied check.
 template <int DC, bool BP, int MT>
 __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, bool unsat, float gs, float gu,
-                                          uint32_t (&c2v)[DC]) {
+                                          float (&c2v)[DC]) {
     const uint32_t par = xor_signs<DC>(v, sb);  // parity in the sign bit only
     if constexpr (BP) {
         float mag[DC];
         bp_magnitudes<DC>(v, mag);
 #pragma unroll
-        for (int p = 0; p < DC; ++p) c2v[p] = bits(mag[p]) | ((bits(v[p]) ^ par) & kSign);
+        for (int p = 0; p < DC; ++p) c2v[p] = __uint_as_float(bits(mag[p]) | ((bits(v[p]) ^ par) & kSign));
     } else {
         const float alpha = unsat ? gu : gs;
-        // FP16: the v2c values come out of inline assembly, which fminf would
-        // first canonicalize (one more instruction each); the median with
-        // -inf is the same minimum for these non-NaN values.  The infinities
-        // are hidden from the compiler, which would fold a median with a
-        // constant infinity back into a minimum or maximum.
-        float ninf = -__builtin_inff(), pinf = __builtin_inff();
-        if constexpr (MT == SAGMS_MSG_FP16) asm("" : "+v"(ninf), "+v"(pinf));
-        float m1 = fabsf(v[0]), m2 = pinf;
+        float m1 = fabsf(v[0]), m2 = __builtin_inff();
 #pragma unroll
         for (int p = 1; p < DC; ++p) {
             float x = fabsf(v[p]);
             m2 = __builtin_amdgcn_fmed3f(m1, x, m2);
-            if constexpr (MT == SAGMS_MSG_FP16)
-                m1 = __builtin_amdgcn_fmed3f(m1, x, ninf);
-            else
-                m1 = fminf(m1, x);
+            m1 = fminf(m1, x);
         }
         // two products per check, both magnitudes pre-signed with the check
         // parity; per edge: compare, select, and one 3-input bit operation
@@ -250,9 +211,6 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, boo
             const float sa = __uint_as_float(xor_and(bits(alpha), par, kSign));
             S1 = bits(sa * m1);
             S2 = bits(sa * m2);
-        } else if constexpr (MT == SAGMS_MSG_FP16) {
-            S1 = or_and(half_hi(alpha * quantize<MT>(m1)), par, kSign);
-            S2 = or_and(half_hi(alpha * quantize<MT>(m2)), par, kSign);
         } else {
             S1 = or_and(bits(quantize<MT>(alpha * quantize<MT>(m1))), par, kSign);
             S2 = or_and(bits(quantize<MT>(alpha * quantize<MT>(m2))), par, kSign);
@@ -261,62 +219,10 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, boo
 #pragma unroll
         for (int p = 0; p < DC; ++p) {
             const uint32_t sel = fabsf(v[p]) == m1 ? S2 : S1;
-            c2v[p] = xor_and(sel, bits(v[p]), kSign);
+            c2v[p] = __uint_as_float(xor_and(sel, bits(v[p]), kSign));
         }
     }
 }
-
-// A check's own previous outputs between rounds, for v2c = posterior - c2v.
-// FP32 and INT6: one FP32 value per edge.  FP16: the output words as
-// computed (the half in the high 16 bits) for one-block codes (CPL = 1),
-// whose registers are not scarce; two halves per register (edge 2j in the
-// low half, 2j + 1 in the high half) for the larger codes, whose check
-// outputs take most of their registers.
-template <int MT, int DC, int CPL>
-struct OwnOutputs {
-    float r[DC];
-    __device__ __forceinline__ void clear() {
-#pragma unroll
-        for (int p = 0; p < DC; ++p) r[p] = 0.0f;
-    }
-    __device__ __forceinline__ float v2c(int p, float post) const { return post - r[p]; }
-    __device__ __forceinline__ void keep(const uint32_t (&c2v)[DC]) {
-#pragma unroll
-        for (int p = 0; p < DC; ++p) r[p] = __uint_as_float(c2v[p]);
-    }
-};
-
-template <int DC>
-struct OwnOutputs<SAGMS_MSG_FP16, DC, 1> {
-    uint32_t r[DC];
-    __device__ __forceinline__ void clear() {
-#pragma unroll
-        for (int p = 0; p < DC; ++p) r[p] = 0u;
-    }
-    __device__ __forceinline__ float v2c(int p, float post) const { return half_sub<1>(r[p], post); }
-    __device__ __forceinline__ void keep(const uint32_t (&c2v)[DC]) {
-#pragma unroll
-        for (int p = 0; p < DC; ++p) r[p] = c2v[p];
-    }
-};
-
-template <int DC, int CPL>
-struct OwnOutputs<SAGMS_MSG_FP16, DC, CPL> {
-    uint32_t r[(DC + 1) / 2];
-    __device__ __forceinline__ void clear() {
-#pragma unroll
-        for (int j = 0; j < (DC + 1) / 2; ++j) r[j] = 0u;
-    }
-    __device__ __forceinline__ float v2c(int p, float post) const {
-        return p & 1 ? half_sub<1>(r[p >> 1], post) : half_sub<0>(r[p >> 1], post);
-    }
-    // c2v: the halves in the high 16 bits
-    __device__ __forceinline__ void keep(const uint32_t (&c2v)[DC]) {
-#pragma unroll
-        for (int j = 0; j < DC / 2; ++j) r[j] = __builtin_amdgcn_perm(c2v[2 * j + 1], c2v[2 * j], 0x07060302u);
-        if constexpr (DC % 2) r[DC / 2] = c2v[DC - 1] >> 16;
-    }
-};
 
 // One wave's decoder for one code: graph tables and priors held in
 // registers, loaded once (load) and reused for every frame (frame).  The LDS
@@ -385,9 +291,11 @@ struct WaveDecoder {
             post[k] = L0[k];
             lds[LY::POST0 + k * 64 + lane] = L0[k];
         }
-        OwnOutputs<MT, DC, CPL> own[CPL];
+        float c2v[CPL][DC];
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) own[k].clear();
+        for (int k = 0; k < CPL; ++k)
+#pragma unroll
+            for (int p = 0; p < DC; ++p) c2v[k][p] = 0.0f;
         wave_lds_sync();
 
         int it = 0;
@@ -404,7 +312,7 @@ struct WaveDecoder {
 #pragma unroll
                 for (int p = 0; p < DC; ++p) {
                     pj[p] = lds[caddr[k][p]];
-                    v[k][p] = own[k].v2c(p, pj[p]);  // rounded only through the check output
+                    v[k][p] = pj[p] - c2v[k][p];  // rounded only through the check output
                 }
                 unsat[k] = (int32_t)xor_signs<DC>(pj, sb[k]) < 0;
                 w += __builtin_popcountll(ballot(unsat[k]));
@@ -424,11 +332,9 @@ struct WaveDecoder {
             const float gs = gg.x, gu = gg.y;
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
-                uint32_t c2v[DC];
-                cn_update<DC, BP, MT>(v[k], sb[k], unsat[k], gs, gu, c2v);
+                cn_update<DC, BP, MT>(v[k], sb[k], unsat[k], gs, gu, c2v[k]);
 #pragma unroll
-                for (int p = 0; p < DC; ++p) lds[p * LY::CW + k * 64 + lane] = __uint_as_float(c2v[p]);
-                own[k].keep(c2v);
+                for (int p = 0; p < DC; ++p) lds[p * LY::CW + k * 64 + lane] = c2v[k][p];
             }
             wave_lds_sync();
             // VN update: posterior in the graph's summation order
@@ -436,12 +342,7 @@ struct WaveDecoder {
             for (int k = 0; k < VPL; ++k) {
                 float s = L0[k];
 #pragma unroll
-                for (int r = 0; r < DV; ++r) {
-                    if constexpr (MT == SAGMS_MSG_FP16)
-                        s = half_add_hi(__float_as_uint(lds[vaddr[k][r]]), s);
-                    else
-                        s = s + lds[vaddr[k][r]];
-                }
+                for (int r = 0; r < DV; ++r) s = s + lds[vaddr[k][r]];
                 post[k] = s;
                 lds[LY::POST0 + k * 64 + lane] = s;
             }
