@@ -21,9 +21,10 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
     using LY = Lay<DC, CPL, VPL>;
     extern __shared__ float lds_all[];
     const int lane = threadIdx.x & 63;
-    // not made wave-uniform: with a uniform wave index the compiler loads the
-    // syndromes with scalar loads, which fetched twice their bytes from HBM
-    const int wib = threadIdx.x >> 6;
+    // wave-uniform, so that the frame index and the output addresses are
+    // scalar values (the syndrome loads are kept vector loads: scalar loads
+    // of them fetched twice their bytes from HBM)
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float* lds = lds_all + wib * LY::WORDS;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
     if (wave >= ws.wave0[ws.levels]) return;

@@ -28,6 +28,7 @@
 // every later value is a sum or a difference of finite floats starting from
 // it), so sign bits and "< 0" agree and the kernel uses sign bits.
 #include <hip/hip_fp16.h>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -263,9 +264,16 @@ struct WaveDecoder {
     // Original syndrome bits of frame f for the lane's checks, at the sign
     // position (checks beyond m read as 0; their rows hold only the +inf
     // padding).
+    // (a vector load: the address is moved to vector registers, since scalar
+    // loads of the syndromes fetched twice their bytes from HBM; it stays a
+    // global-memory pointer, so that the load is not a flat load, which the
+    // LDS waits would also wait for)
     __device__ __forceinline__ static void load_syndrome(const DecodeArgs& a, int64_t f, uint64_t (&word)[CPL]) {
+        using GlobalWord = const __attribute__((address_space(1))) uint64_t;
+        GlobalWord* row = (GlobalWord*)(a.synd + f * a.wm);  // address-space cast
+        asm("" : "+v"(row));
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) word[k] = k < a.wm ? a.synd[f * a.wm + k] : 0ull;
+        for (int k = 0; k < CPL; ++k) word[k] = k < a.wm ? row[k] : 0ull;
     }
     __device__ __forceinline__ static void syndrome_bits(const DecodeArgs& a, int lane, const uint64_t (&word)[CPL],
                                                          uint32_t (&sb)[CPL]) {
@@ -291,17 +299,18 @@ struct WaveDecoder {
             post[k] = L0[k];
             lds[LY::POST0 + k * 64 + lane] = L0[k];
         }
+        // the check's own previous outputs: written by the first round
+        // before any read (the first round's are zero and not subtracted)
         float c2v[CPL][DC];
-#pragma unroll
-        for (int k = 0; k < CPL; ++k)
-#pragma unroll
-            for (int p = 0; p < DC; ++p) c2v[k][p] = 0.0f;
         wave_lds_sync();
 
         int it = 0;
         bool conv = false;
-        // one round; false once the frame is done
-        auto round = [&]() -> bool {
+        // one round; false once the frame is done.  first: the frame's first
+        // round, whose v2c messages are the posteriors themselves (its own
+        // previous outputs are zero, and x - 0 is x bit for bit)
+        auto round = [&](auto first) -> bool {
+            constexpr bool FIRST = decltype(first)::value;
             // top of the round: v2c, hard-decision parity, residual syndrome
             float v[CPL][DC];
             bool unsat[CPL];  // residual syndrome bit: s xor (H e_hat) of the check
@@ -312,7 +321,7 @@ struct WaveDecoder {
 #pragma unroll
                 for (int p = 0; p < DC; ++p) {
                     pj[p] = lds[caddr[k][p]];
-                    v[k][p] = pj[p] - c2v[k][p];  // rounded only through the check output
+                    v[k][p] = FIRST ? pj[p] : pj[p] - c2v[k][p];  // rounded only through the check output
                 }
                 unsat[k] = (int32_t)xor_signs<DC>(pj, sb[k]) < 0;
                 w += __builtin_popcountll(ballot(unsat[k]));
@@ -349,10 +358,13 @@ struct WaveDecoder {
             wave_lds_sync();
             return true;
         };
-        while (round()) {
-            if constexpr (UR == 2)
-                if (!round()) break;
-        }
+        using First = std::integral_constant<bool, true>;
+        using Later = std::integral_constant<bool, false>;
+        if (round(First{}))
+            while (round(Later{})) {
+                if constexpr (UR == 2)
+                    if (!round(Later{})) break;
+            }
 
         syndrome_bits(a, lane, next_word, sb);
         // take the prefetched bits before the output stores are issued: a
