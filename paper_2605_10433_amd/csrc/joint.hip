@@ -69,6 +69,19 @@ __device__ __forceinline__ JointVar joint_var(float l0, float sx, float sz) {
     return v;
 }
 
+// Syndrome words of frame f (a vector load: the wave-uniform address is
+// moved to vector registers, since scalar loads of the syndromes fetched
+// twice their bytes from HBM; still a global-memory pointer, so that the
+// load is not a flat load, which the LDS waits would also wait for).
+template <int CPL>
+__device__ __forceinline__ void joint_syndrome(const uint64_t* synd, int wm, int64_t f, uint64_t (&word)[CPL]) {
+    using GlobalWord = const __attribute__((address_space(1))) uint64_t;
+    GlobalWord* row = (GlobalWord*)(synd + f * wm);  // address-space cast
+    asm("" : "+v"(row));
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) word[k] = k < wm ? row[k] : 0ull;
+}
+
 // At most 128 VGPRs: four resident wavefronts per SIMD.
 template <int DC, int DV, int CPL, int VPL>
 __global__ void __launch_bounds__(64 * kJointWavesPerBlock) __attribute__((amdgpu_waves_per_eu(4)))
@@ -77,7 +90,8 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
     constexpr int DVH = DV / 2;
     extern __shared__ float jlds_all[];
     const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;
+    // wave-uniform: frame index and output addresses are scalar values
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float* lds = jlds_all + wib * LY::WORDS;
     float2* pairx = reinterpret_cast<float2*>(lds + LY::PAIRX);
     float2* pairz = reinterpret_cast<float2*>(lds + LY::PAIRZ);
@@ -108,14 +122,16 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
     write_gains(a.gains, a.m, LY::CW + 1, lds + LY::GAIN0, lane);
     lds[LY::ZERO + lane] = 0.0f;
     reinterpret_cast<float2*>(lds + LY::PADPAIR)[lane] = make_float2(__builtin_inff(), 0.0f);
-
+    // the syndrome words of the wave's next frame are loaded while the
+    // current frame decodes
+    uint64_t word[CPL];
+    joint_syndrome<CPL>(a.synd, a.wm, f_begin, word);
     for (int64_t f = f_begin; f < f_end; ++f) {
         uint32_t sb[CPL];  // original syndrome bits at the sign position
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            const uint64_t word = k < a.wm ? a.synd[f * a.wm + k] : 0ull;
-            sb[k] = (k * 64 + lane < a.m) ? (uint32_t)((word >> lane) & 1ull) << 31 : 0u;
-        }
+        for (int k = 0; k < CPL; ++k)
+            sb[k] = (k * 64 + lane < a.m) ? (uint32_t)((word[k] >> lane) & 1ull) << 31 : 0u;
+        joint_syndrome<CPL>(a.synd, a.wm, f + 1 < f_end ? f + 1 : f, word);
         // round 0: beliefs are the prior
         JointVar var[VPL];
 #pragma unroll
@@ -124,16 +140,17 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
             pairx[k * 64 + lane] = var[k].px;
             pairz[k * 64 + lane] = var[k].pz;
         }
+        // the check's own previous outputs: written by the first round before
+        // any read (the first round's are zero and not subtracted)
         float c2v[CPL][DC];
-#pragma unroll
-        for (int k = 0; k < CPL; ++k)
-#pragma unroll
-            for (int p = 0; p < DC; ++p) c2v[k][p] = 0.0f;
         wave_lds_sync();
 
         int it = 0;
         bool conv = false;
-        while (true) {
+        // one round; false once the frame is done.  first: the frame's first
+        // round (A - 0 is A bit for bit)
+        auto round = [&](auto first) -> bool {
+            constexpr bool FIRST = decltype(first)::value;
             // top of the round: scalar messages, residual syndrome
             float v[CPL][DC];
             bool unsat[CPL];
@@ -146,7 +163,7 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
                 float wv[DC];
 #pragma unroll
                 for (int p = 0; p < DC; ++p) {
-                    v[k][p] = (pw[p].x - c2v[k][p]) + fabsf(pw[p].y);
+                    v[k][p] = (FIRST ? pw[p].x : pw[p].x - c2v[k][p]) + fabsf(pw[p].y);
                     wv[p] = pw[p].y;
                 }
                 // the decision bits ride in the sign bits of the W's
@@ -155,9 +172,9 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
             }
             if (w == 0) {
                 conv = true;
-                break;
+                return false;
             }
-            if (it == a.lmax) break;
+            if (it == a.lmax) return false;
             ++it;
             const float2 gg = *reinterpret_cast<const float2*>(&lds[LY::GAIN0 + 2 * w]);
             // check update: min1 / min2 / sign parity, saturated magnitudes
@@ -196,7 +213,15 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
                 pairz[k * 64 + lane] = var[k].pz;
             }
             wave_lds_sync();
-        }
+            return true;
+        };
+        if (round(std::integral_constant<bool, true>{}))
+            while (round(std::integral_constant<bool, false>{})) {
+            }
+        // take the prefetched words before the output stores are issued: a
+        // wait placed after them would also wait for the stores
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) asm volatile("" ::"v"(word[k]));
 
         // outputs: x_hat words, then z_hat words; rounds; flag; beliefs
         const int wn = a.wn;
