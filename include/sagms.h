@@ -450,8 +450,9 @@ int sagms_decode_segments(const sagms_segment* segs, int32_t nseg, const sagms_d
  * finished launches (their outputs are copied to the requests' host buffers
  * and their completions recorded), then, while one of the server's streams
  * is free, takes the class whose oldest waiting request is oldest among the
- * classes ready to launch (min_launch_frames waiting, or max_wait_us
- * exceeded, or no launch in flight) and admits requests from it in order
+ * classes ready to launch (min_launch_frames waiting; or max_wait_us
+ * exceeded while fewer than half of the streams, rounded up, are busy; or
+ * no launch in flight) and admits requests from it in order
  * while the launch holds at most
  * max_frames_per_launch frames and all launches in flight at most
  * max_frames_in_flight frames (the device-memory budget); the admitted
@@ -469,8 +470,9 @@ typedef struct {
     int32_t min_launch_frames;     /* a class is launched once it has this many
                                       frames waiting (0 .. max_frames_per_launch), */
     double max_wait_us;            /* or once its oldest request has waited this
-                                      long (>= 0), or at once when nothing is
-                                      in flight                               */
+                                      long (>= 0) while fewer than half of the
+                                      streams are busy, or at once when
+                                      nothing is in flight                    */
     int32_t streams;               /* launches in flight at once, 1 .. 8     */
     int32_t tile_frames;           /* persistent-kernel tile, 1 .. 1024      */
     int32_t waves_per_block;       /* 1, 2 or 4 (halved where LDS needs it)  */

@@ -219,19 +219,27 @@ int progress(Server* s, int* retired) {
                 }
             }
         }
+    // a class launches on its waiting time only while fewer than half of the
+    // streams (rounded up) are busy: under light load fewer launches share
+    // the GPU and each finishes sooner; under load the frame count starts
+    // the others
+    int busy = 0;
+    for (const Slot& x : s->slots) busy += x.busy ? 1 : 0;
+    const int eager = (s->scfg.streams + 1) / 2;
     for (Slot& x : s->slots) {
         if (x.busy) continue;
         int tier = -1;
         for (int k = 0; k < kNumMixedTiers; ++k) {
             if (s->lane[k].empty()) continue;
             const bool ready = s->in_flight == 0 || s->lane_frames[k] >= s->scfg.min_launch_frames ||
-                               t - s->lane[k].front().submit_us >= s->scfg.max_wait_us;
+                               (busy < eager && t - s->lane[k].front().submit_us >= s->scfg.max_wait_us);
             if (ready && (tier < 0 || s->lane[k].front().submit_us < s->lane[tier].front().submit_us)) tier = k;
         }
         if (tier < 0) break;
         if (s->lane[tier].front().r.nframes > s->scfg.max_frames_in_flight - s->in_flight) break;  // budget full
         int rc = launch(s, x, tier, t);
         if (rc) return rc;
+        busy += x.busy ? 1 : 0;
     }
     return SAGMS_OK;
 }
