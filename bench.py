@@ -382,7 +382,8 @@ def run_serve(args):
     at the offered loads (fractions of the serving-format batch throughput),
     replayed in real time by the server; one JSON line per load with p50 /
     p99 latency and served throughput beside the FP32 batch."""
-    for out in serve_measure(args, workloads_serve_loads()):
+    loads = [float(x) for x in args.serve_loads.split(",")] if args.serve_loads else workloads_serve_loads()
+    for out in serve_measure(args, loads):
         print(json.dumps(out), flush=True)
 
 
@@ -558,6 +559,7 @@ def main():
     ap.add_argument("--serve-launch-frames", type=int, default=1 << 17, help="serve: max frames per launch")
     ap.add_argument("--serve-streams", type=int, default=4, help="serve: launches in flight")
     ap.add_argument("--serve-tile", type=int, default=8, help="serve: frames per queue tile")
+    ap.add_argument("--serve-loads", default="", help="serve: offered loads, comma-separated (default 0.5,0.8)")
     ap.add_argument("--serve-min-frames", type=int, default=65536,
                     help="serve: frames a class accumulates before it is launched while others run")
     ap.add_argument("--serve-max-wait-us", type=float, default=1000.0,
