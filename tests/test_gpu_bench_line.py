@@ -1,9 +1,9 @@
 """The bench's result line on the GPU: a short run of bench.py (two timed
 steps of the l = 63 workload) prints one JSON line with the fields its
 readers rely on: the metric and its unit, the timed steps, one GPU, the
-configuration, the roofline object of the decode kernel (with the survey's
-14-operation fraction), the FP16 pass over the same frames and the serving
-latency at 80 % load.  The mixed-code workload's line, after the plan
+configuration, the roofline object of the decode kernel (with the fraction
+by the 14-operation count fixed before tuning), the FP16 pass over the same
+frames and the serving latency at 80 % load.  The mixed-code workload's line, after the plan
 autotuner, names the tuned plan and the tuner's log."""
 import json
 import os
@@ -43,7 +43,7 @@ def test_bench_prints_one_complete_line():
     assert 0 < rl["frac"] <= 1 and rl["frac"] == pytest.approx(rl["achieved"] / rl["peak"], rel=1e-9)
     # the whole step takes at least as long as its decode
     assert out["decode_ms_per_step"] <= out["ms_per_step"]
-    assert rl["frac_survey_14_ops"] == pytest.approx(rl["frac"] * 14 / rl["ops_per_edge_update"], rel=1e-9)
+    assert rl["frac_14_ops"] == pytest.approx(rl["frac"] * 14 / rl["ops_per_edge_update"], rel=1e-9)
     assert "counters" in rl
     f16 = out["fp16"]
     assert f16["value"] > 0 and f16["vs_fp32"] == pytest.approx(f16["value"] / out["value"], rel=1e-9)
