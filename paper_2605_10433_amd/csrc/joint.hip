@@ -132,13 +132,15 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
         for (int k = 0; k < CPL; ++k)
             sb[k] = (k * 64 + lane < a.m) ? (uint32_t)((word[k] >> lane) & 1ull) << 31 : 0u;
         joint_syndrome<CPL>(a.synd, a.wm, f + 1 < f_end ? f + 1 : f, word);
-        // round 0: beliefs are the prior
-        JointVar var[VPL];
+        // round 0: beliefs are the prior.  Only the decisions of the latest
+        // beliefs are kept through the rounds (bit 0: x_hat, bit 1: z_hat)
+        uint32_t dec[VPL];
 #pragma unroll
         for (int k = 0; k < VPL; ++k) {
-            var[k] = joint_var(L0[k], 0.0f, 0.0f);
-            pairx[k * 64 + lane] = var[k].px;
-            pairz[k * 64 + lane] = var[k].pz;
+            const JointVar v0 = joint_var(L0[k], 0.0f, 0.0f);
+            pairx[k * 64 + lane] = v0.px;
+            pairz[k * 64 + lane] = v0.pz;
+            dec[k] = (v0.xh ? 1u : 0u) | (v0.zh ? 2u : 0u);
         }
         // the check's own previous outputs: written by the first round before
         // any read (the first round's are zero and not subtracted)
@@ -208,9 +210,10 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
                 float sz = lds[vaddr[k][DVH]];
 #pragma unroll
                 for (int r = DVH + 1; r < DV; ++r) sz = sz + lds[vaddr[k][r]];
-                var[k] = joint_var(L0[k], sx, sz);
-                pairx[k * 64 + lane] = var[k].px;
-                pairz[k * 64 + lane] = var[k].pz;
+                const JointVar vk = joint_var(L0[k], sx, sz);
+                pairx[k * 64 + lane] = vk.px;
+                pairz[k * 64 + lane] = vk.pz;
+                dec[k] = (vk.xh ? 1u : 0u) | (vk.zh ? 2u : 0u);
             }
             wave_lds_sync();
             return true;
@@ -229,7 +232,7 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
 #pragma unroll
         for (int k = 0; k < VPL; ++k) {
             const int j = k * 64 + lane;
-            const uint64_t bx = ballot(j < a.n && var[k].xh), bz = ballot(j < a.n && var[k].zh);
+            const uint64_t bx = ballot(j < a.n && (dec[k] & 1u)), bz = ballot(j < a.n && (dec[k] & 2u));
             if (lane == k) {
                 mx = bx;
                 mz = bz;
@@ -240,14 +243,28 @@ joint_kernel(JointArgs a, WaveSchedule ws) {
             a.ehat[f * 2 * wn + wn + lane] = mz;
         }
         if (a.gamma) {
+            // the final beliefs, recomputed from the last round's check
+            // outputs in their LDS slots (the sums of that round's variable
+            // update, in the same order; the prior's when no round ran), so
+            // that no register holds them through the rounds
 #pragma unroll
             for (int k = 0; k < VPL; ++k) {
+                float sx = 0.0f, sz = 0.0f;
+                if (it > 0) {
+                    sx = lds[vaddr[k][0]];
+#pragma unroll
+                    for (int r = 1; r < DVH; ++r) sx = sx + lds[vaddr[k][r]];
+                    sz = lds[vaddr[k][DVH]];
+#pragma unroll
+                    for (int r = DVH + 1; r < DV; ++r) sz = sz + lds[vaddr[k][r]];
+                }
+                const JointVar vk = joint_var(L0[k], sx, sz);
                 const int j = k * 64 + lane;
                 if (j < a.n) {
                     float* g = a.gamma + (f * a.n + j) * 3;
-                    g[0] = var[k].gx;
-                    g[1] = var[k].gy;
-                    g[2] = var[k].gz;
+                    g[0] = vk.gx;
+                    g[1] = vk.gy;
+                    g[2] = vk.gz;
                 }
             }
         }
