@@ -163,6 +163,20 @@ __device__ __forceinline__ float quantize(float x) {
     }
 }
 
+// FP16 rounding of two values at once, each exactly quantize<FP16>: one
+// packed conversion (nearest even), one packed minimum with the largest half
+// (a value at or above the largest half converts to it or to +inf, which the
+// minimum brings back to it: the saturation of quantize), two widenings.
+// For the non-negative magnitudes of a check update.
+typedef _Float16 half2_v __attribute__((ext_vector_type(2)));
+typedef float float2_v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2_v quantize_fp16_pair(float a, float b) {
+    const float2_v x = {a, b};
+    const half2_v cap = {(_Float16)65504.0f, (_Float16)65504.0f};
+    const half2_v h = __builtin_elementwise_min(__builtin_convertvector(x, half2_v), cap);
+    return __builtin_convertvector(h, float2_v);
+}
+
 // The prior as the decoder uses it: -0 read as +0; INT6 puts it on the
 // message grid, FP16 on the grid of step 2^-24 (magnitudes >= 1 already are).
 template <int MT>
@@ -212,6 +226,12 @@ __device__ __forceinline__ void cn_update(const float (&v)[DC], uint32_t sb, boo
             const float sa = __uint_as_float(xor_and(bits(alpha), par, kSign));
             S1 = bits(sa * m1);
             S2 = bits(sa * m2);
+        } else if constexpr (MT == SAGMS_MSG_FP16) {
+            // the two magnitudes and the two products rounded pairwise
+            const float2_v q = quantize_fp16_pair(m1, m2);
+            const float2_v o = quantize_fp16_pair(alpha * q.x, alpha * q.y);
+            S1 = or_and(bits(o.x), par, kSign);
+            S2 = or_and(bits(o.y), par, kSign);
         } else {
             S1 = or_and(bits(quantize<MT>(alpha * quantize<MT>(m1))), par, kSign);
             S2 = or_and(bits(quantize<MT>(alpha * quantize<MT>(m2))), par, kSign);
