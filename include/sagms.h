@@ -137,9 +137,15 @@ typedef struct {
     int32_t joint;         /* 1 for a joint graph (sagms_build_gb_joint)      */
     int32_t words_e;       /* words per estimate frame: words_n, or 2 words_n
                               (x part, then z part) for a joint graph         */
-    int32_t layered_group; /* SAGMS_LAYERED: lanes per frame (4 .. 64), or 0
-                              when the layered schedule cannot run the graph */
-    int32_t layered_passes;/* SAGMS_LAYERED: passes per round (0 likewise)    */
+    int32_t layered_group; /* SAGMS_LAYERED: lanes per frame: 8 .. 64, or 1
+                              for the matrix compiled into the one-lane
+                              kernel (the l = 63 GB code's H_Z, rows in
+                              sagms_build_gb's order); 0 when the layered
+                              schedule cannot run the graph              */
+    int32_t layered_passes;/* SAGMS_LAYERED: passes per round, one check per
+                              lane of a group in each (m for the one-lane
+                              kernel: a lane updates every check in turn);
+                              0 likewise                                  */
 } sagms_graph_info_t;
 
 /* ---- graphs (host only; no device needed) ----------------------------- */
@@ -515,7 +521,9 @@ int sagms_server_create(const sagms_graph* graphs, const float* const* llr0_host
 int sagms_server_submit(sagms_server s, const sagms_request* req, int64_t* id);
 
 /* One progress step (retire, then admit and launch; never blocks), then
- * returns up to cap completions in order of completion. */
+ * returns up to cap completions in order of completion.  A launch that
+ * cannot be enqueued returns its error and leaves its requests queued, in
+ * their order (the step then waits for that stream). */
 int sagms_server_progress(sagms_server s, sagms_completion* done, int32_t cap, int32_t* ndone);
 
 /* Requests waiting, frames in launches in flight, completions not yet returned. */

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsagms.so")
 SOURCES = ["graph.cpp", "api.cpp", "batch.cpp", "serve.cpp", "layers.cpp", "decode.hip", "mixed.hip", "sample.hip",
-           "judge.hip", "layered.hip", "joint.hip"]
+           "judge.hip", "layered.hip", "layered_lane.hip", "joint.hip"]
 ARCH = "gfx950"
 
 

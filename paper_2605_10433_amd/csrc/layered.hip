@@ -397,8 +397,12 @@ int launch_d(int G, bool regs, const LayeredArgs& la, size_t lds, int num_cu, hi
 
 }  // namespace
 
+// One lane per frame for the compiled l = 63 code (layered_lane.hip).
+int launch_layered_lane(const DecodeArgs& a, hipStream_t st);
+
 int launch_layered(const LayeredPlan& plan, const DecodeArgs& a, hipStream_t st) {
     if (a.nframes <= 0) return SAGMS_OK;
+    if (plan.group == 1) return launch_layered_lane(a, st);
     LayeredArgs la{};
     la.a = a;
     la.pass_check = plan.pass_check;

@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "lane_code.h"
 
 namespace sagms {
 
@@ -18,6 +19,21 @@ constexpr double kLdsFormCost = 1.18;
 constexpr int kLdsPerCu = 163840;  // bytes of LDS per compute unit
 
 int round4(int x) { return (x + 3) & ~3; }
+
+// True when g's rows are those compiled into the one-lane kernel (as sets:
+// the order of a row's variables does not change any result).
+bool is_lane_code(const Graph* g) {
+    if (g->m != lane::kL || g->n != lane::kN) return false;
+    for (int c = 0; c < lane::kL; ++c) {
+        if (g->row_ptr[c + 1] - g->row_ptr[c] != lane::kDC) return false;
+        std::vector<int> mine(g->cols.begin() + g->row_ptr[c], g->cols.begin() + g->row_ptr[c + 1]);
+        std::vector<int> want(lane::kRows.var[c], lane::kRows.var[c] + lane::kDC);
+        std::sort(mine.begin(), mine.end());
+        std::sort(want.begin(), want.end());
+        if (mine != want) return false;
+    }
+    return true;
+}
 
 // LDS words of one frame's slice.  Every group of a wavefront updates the
 // same check in the same pass, so its lanes read the same offsets of their
@@ -83,6 +99,26 @@ static int plan(const Graph* g, LayeredHost* lh) {
     // passes x G, with the LDS form of the outputs weighted by its measured
     // extra cost and plans with fewer than 8 resident wavefronts per CU by
     // the missing ones; on a tie the larger G (the shorter pass chain).
+    // The compiled l = 63 code: one lane per frame updates the checks one
+    // after another in (layer, position) order, the order of these layers.
+    if (is_lane_code(g)) {
+        std::vector<int32_t> order;
+        for (const auto& l : layers) order.insert(order.end(), l.begin(), l.end());
+        if (std::equal(order.begin(), order.end(), lane::kOrder.check) && (int)layers.size() == lane::kOrder.layers) {
+            lh->group = 1;
+            lh->passes = m;
+            lh->regs = true;
+            lh->group_words = 0;
+            lh->table_words = 0;
+            lh->pass_check = order;
+            lh->check_vars.assign((size_t)m * (dc / 2), 0u);  // not read by the kernel; kept for the upload
+            lh->dc = dc;
+            lh->npad = round4(n);
+            lh->status = SAGMS_OK;
+            lh->why.clear();
+            return SAGMS_OK;
+        }
+    }
     const int wm = g->wm, wn = g->wn;
     if (wm > 64 || wn > 64) return refuse(lh, "layered schedule: code too long");
     std::vector<int> last(n);

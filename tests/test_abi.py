@@ -431,10 +431,34 @@ def test_layered_plan_packs_passes(name):
     _, hz = codes.gb_matrices(l, a, b)
     g = sagms.Graph.gb(l, a, b)
     G, P = g.layered_group, g.layered_passes
+    if name == "G63":
+        # the compiled code: one lane per frame updates the 63 checks in turn
+        assert (G, P) == (1, 63)
+        return
     assert G in (8, 16, 32, 64) and G >= max(g.words_m, g.words_n)
     assert P == _packed_passes(hz, G)
     assert P <= sum(-(-len(layer) // G) for layer in layered.greedy_layers(hz))
-    if name == "G63":
-        assert (G, P) == (8, 14)   # 14 layers of at most 6 checks form a chain: nothing to pack
     if name == "G511w5":
         assert (G, P) == (32, 21)
+
+
+def test_layered_lane_kernel_only_for_its_matrix():
+    """The one-lane layered kernel runs the l = 63 code's H_Z only: the same
+    matrix given densely (rows in the same order) selects it, whatever the
+    order of each row's entries; the rows in another order or one entry
+    moved do not (the general kernel, groups of 8 or more lanes, or no
+    layered plan at all)."""
+    l, a, b = workloads.code("G63")
+    _, hz = codes.gb_matrices(l, a, b)
+    g = sagms.Graph.from_dense(hz)
+    assert (g.layered_group, g.layered_passes) == (1, 63)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(hz.shape[0])
+    g = sagms.Graph.from_dense(hz[perm])
+    assert g.layered_group >= 8
+    h = hz.copy()
+    row = h[5]
+    on, off = np.nonzero(row)[0][0], np.nonzero(row == 0)[0][0]
+    row[on], row[off] = 0, 1
+    g = sagms.Graph.from_dense(h)
+    assert g.layered_group != 1

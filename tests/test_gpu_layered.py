@@ -149,6 +149,64 @@ def test_layered_full_size(dev):
     assert (buf["converged"].cpu().numpy()[pick].astype(bool) == r.converged).all()
 
 
+@pytest.mark.parametrize("kind,kw", KINDS)
+def test_layered_general_kernel_on_the_l63_code(dev, kind, kw):
+    """The l = 63 matrix with its rows permuted is not the compiled matrix of
+    the one-lane kernel, so it runs on the general kernel (groups of lanes):
+    against the oracle's layered FP32 mode on the permuted matrix."""
+    l, a, b = workloads.code("G63")
+    hz = codes.gb_matrices(l, a, b)[1]
+    perm = np.random.default_rng(8).permutation(l)
+    h = hz[perm]
+    g = sagms.Graph.from_dense(h)
+    assert g.layered_group >= 8
+    ex, _ = channel.sample_paulis(3, 6, 0, 700, 2 * l, 0.05)
+    s = channel.syndrome(h, ex)
+    llr = np.full(2 * l, channel.prior_llr(0.05), np.float32)
+    prm = decoders.DecoderParams(kind=kind, lmax=100, **kw)
+    r = layered.decode_layered(decoders.TannerGraph(h), s, llr, prm, "fp32")
+    say("layered general kernel, permuted l = 63 rows", kind)
+    e, it, cv, post = gpu_layered(g, s, llr, sagms.decoder_config(kind, lmax=100, schedule="layered", **kw), dev)
+    assert (it == r.iters).all() and (cv == r.converged).all() and (e == r.ehat).all()
+    ref = np.asarray(r.posterior, np.float32)
+    nan = np.isnan(ref)
+    assert (np.isnan(post) == nan).all()
+    assert (post.view(np.uint32)[~nan] == ref.view(np.uint32)[~nan]).all()
+
+
+def test_layered_lane_kernel_ragged_launch(dev):
+    """The one-lane kernel of the l = 63 code over 2^16 + 37 frames (runs of
+    frames per wavefront that do not divide evenly, a last wavefront with
+    fewer frames than lanes): hard decisions, rounds, flags and posteriors of
+    300 sampled frames, the last 37 among them, against the oracle."""
+    l, a, b = workloads.code("G63")
+    hz = codes.gb_matrices(l, a, b)[1]
+    g = sagms.Graph.gb(l, a, b)
+    assert g.layered_group == 1
+    p, nf = 0.06, (1 << 16) + 37
+    buf = sagms.frame_buffers(g, nf, device=dev)
+    sagms.gen_errors(g, 4, 7, 1 << 33, nf, p, buf["ex"], buf["ez"], buf["synd"])
+    llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
+    post = torch.full((nf, g.n), float("nan"), dtype=torch.float32, device=dev)
+    cfg = sagms.decoder_config("sagms", schedule="layered", **workloads.SAGMS_PARAMS)
+    say("layered one-lane kernel, ragged launch", nf)
+    sagms.decode_soft(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"], post)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    pick = np.unique(np.concatenate([np.arange(nf - 37, nf), rng.integers(0, nf, 263)]))
+    s = channel.unpack(buf["synd"][torch.from_numpy(pick).to(dev)].cpu().numpy().view(np.uint64), l)
+    prm = decoders.DecoderParams(kind="sagms", lmax=100, **workloads.SAGMS_PARAMS)
+    r = layered.decode_layered(decoders.TannerGraph(hz), s, np.full(2 * l, sagms.prior_llr(p), np.float32), prm,
+                               "fp32")
+    e = channel.unpack(buf["ehat"].cpu().numpy().view(np.uint64)[pick], g.n)
+    assert (e == r.ehat).all()
+    assert (buf["iters"].cpu().numpy()[pick] == r.iters).all()
+    assert (buf["converged"].cpu().numpy()[pick].astype(bool) == r.converged).all()
+    got = post.cpu().numpy()[pick]
+    assert (got.view(np.uint32) == np.asarray(r.posterior, np.float32).view(np.uint32)).all()
+    assert (buf["iters"].cpu().numpy() >= 0).all()  # every frame written
+
+
 def test_layered_layer_wider_than_a_wavefront(dev):
     """80 checks with disjoint supports (one layer, wider than a wavefront,
     so it spans several passes whatever the group size) plus 10 checks
