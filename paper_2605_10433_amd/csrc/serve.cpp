@@ -115,7 +115,26 @@ void retire(Server* s, Slot& x, double t) {
     x.busy = false;
 }
 
-// Admits requests of one class into slot x and enqueues its launch.
+// Returns the requests admitted into slot x to the head of their FIFO, in
+// their order, after a launch could not be enqueued.
+void unadmit(Server* s, Slot& x, int tier) {
+    std::deque<Req>& q = s->lane[tier];
+    for (size_t i = x.reqs.size(); i-- > 0;) {
+        const Req& r = x.reqs[i];
+        s->lane_frames[tier] += r.r.nframes;
+        if (r.r.deadline_us > 0.0) ++s->with_deadline;
+        q.push_front(r);
+    }
+    s->queued += (int64_t)x.reqs.size();
+    x.reqs.clear();
+    x.first.clear();
+    x.segs.clear();
+}
+
+int enqueue(Server* s, Slot& x, int tier, int64_t frames, double t);
+
+// Admits requests of one class into slot x and enqueues its launch.  If the
+// launch cannot be enqueued the requests stay queued and the error returns.
 int launch(Server* s, Slot& x, int tier, double t) {
     std::deque<Req>& q = s->lane[tier];
     const int64_t cap = std::min<int64_t>(s->scfg.max_frames_per_launch, s->scfg.max_frames_in_flight - s->in_flight);
@@ -132,6 +151,19 @@ int launch(Server* s, Slot& x, int tier, double t) {
     }
     if (x.reqs.empty()) return SAGMS_OK;
     s->queued -= (int64_t)x.reqs.size();
+    const int rc = enqueue(s, x, tier, frames, t);
+    if (rc) {
+        // the copy in may have been enqueued: let it finish reading the
+        // staging buffer before a later launch refills it
+        (void)hipStreamSynchronize(x.st);
+        unadmit(s, x, tier);
+    }
+    return rc;
+}
+
+// Lays out the admitted requests of slot x as one segment per code, stages
+// their syndromes and enqueues the copy in, the launch and the copy out.
+int enqueue(Server* s, Slot& x, int tier, int64_t frames, double t) {
     // one segment per code, requests in admission order within it
     std::vector<int64_t> seg_of(s->codes.size(), -1);
     for (const Req& r : x.reqs)
