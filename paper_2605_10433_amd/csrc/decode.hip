@@ -12,7 +12,12 @@
 
 namespace sagms {
 
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 4;  // the kernel's bound
+// Waves per block at launch.  A block's LDS is released only when its last
+// wave ends, and the waves of a block finish their runs at different times;
+// blocks of 2 waves kept the l = 63 decode 4 % shorter than blocks of 4 and
+// left the pipelined step's sampler more room than blocks of 1.
+constexpr int kLaunchWavesPerBlock = 2;
 constexpr int kTaperLevels = 2;  // waves per tail level of the tapered schedule, in resident waves
 
 // kg: the gain pairs of one-block codes (CPL == 1); unused otherwise.
@@ -43,10 +48,10 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
     for (int64_t f = f_begin; f < f_end; ++f) d.frame(a, lds, lane, f, sb, f + 1 < f_end ? f + 1 : f, &kg);
 }
 
-// Waves per block: up to kWavesPerBlock, as many as fit in 64 KiB of LDS.
+// Waves per block: up to kLaunchWavesPerBlock, as many as fit in 64 KiB of LDS.
 static int waves_per_block(const DecodeLayout& L) {
     int w = (int)(65536 / ((size_t)L.words * sizeof(float)));
-    return w < 1 ? 1 : (w > kWavesPerBlock ? kWavesPerBlock : w);
+    return w < 1 ? 1 : (w > kLaunchWavesPerBlock ? kLaunchWavesPerBlock : w);
 }
 
 // Host evaluation of the gain law, operation for operation as gain_pair.
