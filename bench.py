@@ -448,7 +448,8 @@ def serve_measure(args, loads):
                                            max_frames_per_launch=args.serve_launch_frames,
                                            min_launch_frames=min(args.serve_min_frames, args.serve_launch_frames),
                                            max_wait_us=args.serve_max_wait_us, streams=args.serve_streams,
-                                           tile_frames=args.serve_tile, waves_per_block=4, reg_budget=1))
+                                           tile_frames=args.serve_tile, waves_per_block=args.serve_waves_per_block,
+                                           reg_budget=1))
     mean_frames = (workloads.SERVE_MAX_FRAMES + 1) / 2.0
 
     def build_trace(k, rate, seconds, seed):
@@ -540,7 +541,8 @@ def serve_measure(args, loads):
                                    % (workloads.SERVE_SEED, workloads.SERVE_MAX_FRAMES, "/".join(workloads.SERVE_CODES),
                                       p, args.decoder.upper(), workloads.SERVE_LMAX, args.precision.upper()),
                        "max_frames_per_launch": args.serve_launch_frames, "streams": args.serve_streams,
-                       "tile_frames": args.serve_tile, "min_launch_frames": args.serve_min_frames,
+                       "tile_frames": args.serve_tile, "waves_per_block": args.serve_waves_per_block,
+                       "min_launch_frames": args.serve_min_frames,
                        "max_wait_us": args.serve_max_wait_us},
         }
         records.append(out)
@@ -563,6 +565,8 @@ def main():
     ap.add_argument("--serve-launch-frames", type=int, default=1 << 17, help="serve: max frames per launch")
     ap.add_argument("--serve-streams", type=int, default=4, help="serve: launches in flight")
     ap.add_argument("--serve-tile", type=int, default=8, help="serve: frames per queue tile")
+    ap.add_argument("--serve-waves-per-block", type=int, default=4, choices=(1, 2, 4),
+                    help="serve: wavefronts per block of the persistent launches")
     ap.add_argument("--serve-loads", default="", help="serve: offered loads, comma-separated (default 0.5,0.8)")
     ap.add_argument("--serve-min-frames", type=int, default=65536,
                     help="serve: frames a class accumulates before it is launched while others run")
