@@ -3,16 +3,16 @@
 //
 // The layered schedule updates the checks one after another; the general
 // kernel (layered.hip) spreads a frame over a group of lanes, which leaves
-// lanes idle when a pass holds fewer checks than the group has lanes and
-// spends a third of each pass unpacking outputs addressed through tables.
-// Here each lane decodes its own frame from start to finish and updates all
-// 63 checks of a round itself, in the order of lane_code.h.  Its 126
-// posteriors and the three words of each check's outputs are registers whose
-// names are fixed at compile time, so a round is straight-line arithmetic: no
-// idle lane, no table read, no LDS access.  The check update is that of the
-// general kernel, operation for operation (S1, S1 xor S2 and the minimum /
-// sign mask of each check; output k is rebuilt from them bit for bit), so
-// the results are the same.
+// lanes idle when a pass holds fewer checks than the group has lanes, and
+// reads its posteriors and tables from LDS.  Here each lane decodes its own
+// frame from start to finish and updates all 63 checks of a round itself, in
+// the order of lane_code.h.  Its 126 posteriors and the three words of each
+// check's outputs are registers whose names are fixed at compile time, so a
+// round is straight-line arithmetic: no idle lane, no table read, no LDS
+// access.  The check update does the general kernel's arithmetic operation
+// for operation and keeps its S1 and S1 xor S2 words; the third word holds
+// edge k's v2c sign at bit 2k and its minimum bit at bit 2k + 1.  Output k
+// is rebuilt from them bit for bit, so the results are the same.
 //
 // A workgroup of four wavefronts (one per SIMD of a compute unit: a lane's
 // state takes the registers of a whole SIMD lane) owns a contiguous run of
