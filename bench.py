@@ -742,16 +742,18 @@ def main():
     edge_updates = sum_iters * g.n_edges
     last = bufs[(args.steps - 1) % len(bufs)]
     it_last = last["iters"].float()
-    # the decode kernel alone (no overlapped sampling): ten more launches, back
-    # to back on the last step's syndromes outside the timed region; the
-    # median of the last five (the clock drops while the host synchronizes)
-    iso_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    # the decode kernel alone (no overlapped sampling): forty more launches,
+    # back to back on the last step's syndromes outside the timed region; the
+    # median of the last twenty (the clock drops while the host synchronizes
+    # and takes about twenty launches to come back: 2.0 ms for the first,
+    # about 1.62 ms from the eighteenth on)
+    iso_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(40)]
     for e0, e1 in iso_ev:
         e0.record(stream)
         sagms.decode(g, last["synd"], llr, cfg, last["ehat"], last["iters"], last["converged"])
         e1.record(stream)
     torch.cuda.synchronize()
-    iso_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in iso_ev[5:]]))
+    iso_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in iso_ev[20:]]))
     iso_ops = ops_per_edge * int(last["iters"].long().sum().item()) * g.n_edges
     iso_achieved = iso_ops / (iso_ms * 1e-3) / 1e12
     mean_dec_ms = float(np.mean(dec_ms))
