@@ -489,10 +489,7 @@ def serve_measure(args, loads):
         rate = load * batch_fps / mean_frames
         # a warm-up trace as long as the timed one, at the same load, is
         # replayed right before it, so that the timed trace starts on a busy,
-        # clocked-up GPU (the host prepares both traces while the GPU idles).
-        # The first timed trace of a process still reads higher than later
-        # ones at the same load (p50 5.8 against 3.7 ms at 80 %; 6.7 against
-        # 3.7 ms after the 50 ms warm-up used before)
+        # clocked-up GPU (the host prepares both traces while the GPU idles)
         warm = build_trace(2 * li, rate, args.serve_seconds, workloads.SERVE_SEED + 1000 + li)
         tr = build_trace(2 * li + 1, rate, args.serve_seconds, workloads.SERVE_SEED)
         code, size = tr["code"], tr["size"]
@@ -789,16 +786,17 @@ def main():
         import copy
         sargs = copy.copy(args)
         sargs.precision, sargs.decoder = "fp16", "sagms"
-        # two timed traces at 80 %, each after its warm-up trace: the first a
-        # process serves reads higher than the later ones (a start-up effect
-        # of the serving process, not of the load); the line reports the
-        # second as the steady state and the first beside it
-        first, rec = serve_measure(sargs, [0.8, 0.8])
+        # two timed traces at 80 %, each after its warm-up trace: traces at
+        # the same load read either about 3.7 ms p50 or 6-13 ms, from run to
+        # run and trace to trace, so the line reports the slower of the two
+        # (by p99) and both under "traces"
+        recs = serve_measure(sargs, [0.8, 0.8])
+        rec = max(recs, key=lambda r: r["p99_us"])
         serving = {k: rec[k] for k in ("p50_us", "p99_us", "mean_us", "offered_load", "offered_frames_per_s",
                                        "served_frames_per_s", "batch_frames_per_s", "fp32_batch_frames_per_s",
                                        "requests", "frames")}
-        serving["first_trace"] = {k: first[k] for k in ("p50_us", "p99_us", "served_frames_per_s",
-                                                        "offered_frames_per_s")}
+        serving["traces"] = [{k: r[k] for k in ("p50_us", "p99_us", "served_frames_per_s", "offered_frames_per_s")}
+                             for r in recs]
         serving["workload"] = rec["config"]["workload"]
     out = {
         "metric": "SAGMS frames/s",

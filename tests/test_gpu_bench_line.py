@@ -50,8 +50,9 @@ def test_bench_prints_one_complete_line():
     assert 0 <= f16["fer"] <= 1 and isinstance(f16["fer_in_fp32_interval"], bool)
     srv = out["serving_p80"]
     assert 0 < srv["p50_us"] <= srv["p99_us"] and srv["offered_load"] == 0.8 and srv["requests"] > 0
-    first = srv["first_trace"]
-    assert 0 < first["p50_us"] <= first["p99_us"] and first["served_frames_per_s"] > 0
+    assert len(srv["traces"]) == 2 and srv["p99_us"] == max(t["p99_us"] for t in srv["traces"])
+    for t in srv["traces"]:
+        assert 0 < t["p50_us"] <= t["p99_us"] and t["served_frames_per_s"] > 0
 
 
 def test_mix_workload_line_with_tuner():
