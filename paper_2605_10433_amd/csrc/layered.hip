@@ -34,11 +34,12 @@
 // round's gains and the exit test.
 //
 // A frame's first residual is its syndrome xor H [L0 < 0], the latter
-// computed once per wavefront.  A wavefront owns a contiguous run of frames.  Each group holds one frame
-// in decoding and one reserved next frame whose syndrome words are already
-// in flight; a group that finishes starts its reserved frame and reserves
-// the next unclaimed frame of the run, so groups stay busy until the run is
-// used up whatever their frames' round counts.
+// computed once per wavefront.  A wavefront owns a contiguous run of frames.
+// A group that has no frame takes the next unclaimed frame of the run and
+// loads its syndrome words then, so groups stay busy until the run is used
+// up whatever their frames' round counts.  (A group holding a claimed next
+// frame while it decoded the current one could leave two long frames for
+// the end of the run.)
 #include "decode_core.h"
 
 namespace sagms {
@@ -120,16 +121,13 @@ layered_kernel(LayeredArgs la) {
     if (f_begin >= f_end) return;
 
     // group state (equal in the G lanes of a group)
-    int64_t f = -1;                              // frame being decoded
-    int64_t res = f_begin + grp < f_end ? f_begin + grp : -1;  // reserved next frame
-    int64_t next = f_begin + F;                  // wave-uniform: next unclaimed frame
-    // lanes q < wm: word q of res's syndrome, its bits at or above m cleared
-    // (the caller's padding bits are not syndrome bits)
+    int64_t f = -1;           // frame being decoded
+    int64_t next = f_begin;   // wave-uniform: next unclaimed frame
+    // lanes q < wm: word q of a frame's syndrome, its bits at or above m
+    // cleared (the caller's padding bits are not syndrome bits)
     const uint64_t keep = q == wm - 1 && (m & 63) ? (1ull << (m & 63)) - 1 : ~0ull;
-    uint64_t res_word = 0;
-    if (res >= 0 && q < wm) res_word = a.synd[res * wm + q] & keep;
     int it = 0, w = 0;
-    bool active = false;
+    bool active = false, more = true;  // more: the run may still hold a frame for this group
     // PMAX > 0: outputs of the lane's check in pass p (S1, S1 ^ S2, mask)
     uint32_t rs1[NREG], rd[NREG], rmk[NREG];
 #pragma unroll
@@ -208,14 +206,21 @@ layered_kernel(LayeredArgs la) {
     };
 
     while (true) {
-        // start reserved frames in idle groups, reserve the next ones, and
-        // finish frames that need no round, until no idle group holds one
+        // idle groups take the next frames of the run (in group order) and
+        // finish frames that need no round, until every group decodes a
+        // frame or the run is used up
         while (true) {
-            const bool start = !active && res >= 0;
-            const uint64_t leaders = __ballot(start && q == 0);
-            if (leaders == 0) break;
+            const bool want = !active && more;
+            const uint64_t takers = __ballot(want && q == 0);
+            if (takers == 0) break;
+            bool start = false;
+            if (want) {
+                f = next + __popcll(takers & ((1ull << (grp * G)) - 1));
+                more = f < f_end;
+                start = more;
+            }
+            next += __popcll(takers);
             if (start) {
-                f = res;
                 for (int j = q; j < n; j += G) post[j] = t_l0[j];
                 if constexpr (PMAX > 0) {
 #pragma unroll
@@ -224,17 +229,13 @@ layered_kernel(LayeredArgs la) {
                     for (int t = q; t < m; t += G) cmp[t] = make_uint4(0u, 0u, 0u, 0u);
                 }
                 if (q < wm) {
-                    sbits[2 * q] = (uint32_t)res_word;
-                    sbits[2 * q + 1] = (uint32_t)(res_word >> 32);
-                    rbits[2 * q] = (uint32_t)res_word ^ t_r0[2 * q];
-                    rbits[2 * q + 1] = (uint32_t)(res_word >> 32) ^ t_r0[2 * q + 1];
+                    const uint64_t word = a.synd[f * wm + q] & keep;
+                    sbits[2 * q] = (uint32_t)word;
+                    sbits[2 * q + 1] = (uint32_t)(word >> 32);
+                    rbits[2 * q] = (uint32_t)word ^ t_r0[2 * q];
+                    rbits[2 * q + 1] = (uint32_t)(word >> 32) ^ t_r0[2 * q + 1];
                 }
-                const int rank = __popcll(leaders & ((1ull << (grp * G)) - 1));
-                const int64_t claim = next + rank;
-                res = claim < f_end ? claim : -1;
-                if (res >= 0 && q < wm) res_word = a.synd[res * wm + q] & keep;
             }
-            next += __popcll(leaders);
             int w0 = 0;
             if (start)
                 for (int t = 0; t < 2 * wm; ++t) w0 += __popc(rbits[t]);
