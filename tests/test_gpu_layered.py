@@ -174,6 +174,20 @@ def test_layered_general_kernel_on_the_l63_code(dev, kind, kw):
     assert (post.view(np.uint32)[~nan] == ref.view(np.uint32)[~nan]).all()
 
 
+@pytest.mark.parametrize("alpha", [0.5, 0.625, 0.875, 1.0])
+def test_layered_lane_kernel_sms_gains(dev, alpha):
+    """SMS with the other gains of the paper's SMS sweep (and 1.0, plain
+    min-sum through the SMS path) on the one-lane kernel of the l = 63 code,
+    two noise levels: bit-exact against the oracle's layered FP32 mode."""
+    l, a, b = workloads.code("G63")
+    hz = codes.gb_matrices(l, a, b)[1]
+    for p, seed in ((0.04, 11), (0.08, 12)):
+        ex, _ = channel.sample_paulis(seed, 6, 0, 800, 2 * l, p)
+        s = channel.syndrome(hz, ex)
+        check_against_oracle("G63", "sms", dict(alpha=alpha), s, np.full(2 * l, channel.prior_llr(p), np.float32),
+                             100, dev)
+
+
 def test_layered_lane_kernel_ragged_launch(dev):
     """The one-lane kernel of the l = 63 code over 2^16 + 37 frames (runs of
     frames per wavefront that do not divide evenly, a last wavefront with
