@@ -376,6 +376,65 @@ def run_mix(args):
     print(json.dumps(out), flush=True)
 
 
+# (code, p) of the per-code decode lines: each code near the noise level of
+# its FER range in the sweeps
+CODES_P = (("G63", 0.05), ("G127", 0.04), ("G255w3", 0.04), ("G255w4", 0.04), ("G511w5", 0.03))
+
+
+def run_codes(args):
+    """sagms_decode alone on 2^20 Philox frames (seed 1, stream 4) of each GB
+    code, with the chosen decoder and schedule: untimed launches for at least
+    0.4 s (the clock comes back from idle over about twenty l = 63 launches),
+    then the median of five, one line per code with frames/s, mean rounds and
+    the fraction of the VALU peak at 8 lane-operations per edge-update."""
+    import torch
+
+    import paper_2605_10433_amd as sagms
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nf = args.frames
+    kw = dict(workloads.SAGMS_PARAMS) if args.decoder == "sagms" else (dict(alpha=args.alpha)
+                                                                        if args.decoder == "sms" else {})
+    only = [c for c in args.codes.split(",") if c] if args.codes else None
+    for name, p in CODES_P:
+        if only is not None and name not in only:
+            continue
+        g = sagms.Graph.gb(*workloads.code(name))
+        buf = sagms.frame_buffers(g, nf, device=dev)
+        sagms.gen_errors(g, 1, 4, 0, nf, p, buf["ex"], buf["ez"], buf["synd"])
+        llr = torch.full((g.n,), sagms.prior_llr(p), dtype=torch.float32, device=dev)
+        cfg = sagms.decoder_config(args.decoder, lmax=args.lmax, schedule=args.schedule, precision=args.precision,
+                                   **kw)
+        w0, w1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0.record()
+        sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
+        w1.record()
+        torch.cuda.synchronize()
+        for _ in range(max(2, int(400.0 / max(w0.elapsed_time(w1), 1e-3)))):
+            sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+        for e0, e1 in ev:
+            e0.record()
+            sagms.decode(g, buf["synd"], llr, cfg, buf["ehat"], buf["iters"], buf["converged"])
+            e1.record()
+        torch.cuda.synchronize()
+        ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+        rounds = float(buf["iters"].double().mean().item())
+        edge_updates = nf * rounds * g.n_edges
+        tops = OPS_PER_EDGE_UPDATE * edge_updates / (ms * 1e-3) / 1e12
+        print(json.dumps({"metric": "decode frames/s", "value": nf / (ms * 1e-3), "unit": "frames/s",
+                          "code": name, "p": p, "decoder": args.decoder, "schedule": args.schedule,
+                          "precision": args.precision, "frames": nf, "decode_ms": ms, "mean_rounds": rounds,
+                          "converged": float(buf["converged"].double().mean().item()),
+                          "layered_group": g.layered_group, "layered_passes": g.layered_passes,
+                          "roofline": {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                                       "frac": tops / VALU_PEAK_TOPS, "ops_per_edge_update": OPS_PER_EDGE_UPDATE}}),
+              flush=True)
+        del buf
+
+
 def run_serve(args):
     """The serving workload (FP16 messages by default): the five-code batch
     throughput first (one tuned sagms_batch_run over equal shares of 2^20
@@ -555,9 +614,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--frames", type=int, default=1 << 20)
     ap.add_argument("--p", type=float, default=None, help="noise level (default 0.05; 0.04 for the mix)")
-    ap.add_argument("--workload", default="g63", choices=["g63", "mix", "serve"],
+    ap.add_argument("--workload", default="g63", choices=["g63", "mix", "serve", "codes"],
                     help="g63: the l = 63 code, 2^20 frames per step; mix: four GB codes, 2^22 frames per step "
-                         "in one batch; serve: Poisson request traces over five codes through the server")
+                         "in one batch; serve: Poisson request traces over five codes through the server; "
+                         "codes: sagms_decode alone on 2^20 frames of each of the five codes (--schedule, "
+                         "--decoder), one line per code")
+    ap.add_argument("--codes", default="", help="codes: comma-separated subset of G63,G127,G255w3,G255w4,G511w5")
     ap.add_argument("--serve-seconds", type=float, default=0.25, help="serve: length of each arrival trace")
     ap.add_argument("--serve-launch-frames", type=int, default=1 << 17, help="serve: max frames per launch")
     ap.add_argument("--serve-streams", type=int, default=4, help="serve: launches in flight")
@@ -615,8 +677,9 @@ def main():
         print(decode_source_sha256())
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the decoder is data-parallel over frames and a multi-GPU run "
-              "would only split the frame range (see the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the decoder is data-parallel over frames, so a run on R GPUs "
+              "would split the frame range and exchange only the two failure counters; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "mix":
@@ -624,6 +687,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "codes":
+        run_codes(args)
         return
     if args.p is None:
         args.p = 0.05

@@ -14,9 +14,11 @@ namespace sagms {
 
 constexpr int kWavesPerBlock = 4;  // the kernel's bound
 // Waves per block at launch.  A block's LDS is released only when its last
-// wave ends, and the waves of a block finish their runs at different times;
-// blocks of 2 waves kept the l = 63 decode 4 % shorter than blocks of 4 and
-// left the pipelined step's sampler more room than blocks of 1.
+// wave ends, and the waves of a block finish their runs at different times.
+// One-block codes (CPL = 1) use blocks of 2: 4 % shorter decodes than blocks
+// of 4 on the l = 63 code, and more room for the pipelined step's sampler
+// than blocks of 1.  Larger codes, whose waves hold 4-8 times the LDS, use
+// blocks of 1 (l = 127 / 255 / 511: 1 / 2.5 / 4.5 % shorter than blocks of 2).
 constexpr int kLaunchWavesPerBlock = 2;
 constexpr int kTaperLevels = 2;  // waves per tail level of the tapered schedule, in resident waves
 
@@ -48,8 +50,10 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) decode_kernel(DecodeArgs 
     for (int64_t f = f_begin; f < f_end; ++f) d.frame(a, lds, lane, f, sb, f + 1 < f_end ? f + 1 : f, &kg);
 }
 
-// Waves per block: up to kLaunchWavesPerBlock, as many as fit in 64 KiB of LDS.
-static int waves_per_block(const DecodeLayout& L) {
+// Waves per block: for one-block codes up to kLaunchWavesPerBlock, as many as
+// fit in 64 KiB of LDS; 1 for larger codes.
+static int waves_per_block(const DecodeLayout& L, int cpl) {
+    if (cpl > 1) return 1;
     int w = (int)(65536 / ((size_t)L.words * sizeof(float)));
     return w < 1 ? 1 : (w > kLaunchWavesPerBlock ? kLaunchWavesPerBlock : w);
 }
@@ -124,7 +128,7 @@ static int launch_shape(bool bp, int mt, const DecodeArgs& a, hipStream_t st) {
         a.L.gain0 != LY::GAIN0 || a.L.words != LY::WORDS)
         return fail(SAGMS_EUNSUPPORTED, "decode layout mismatch (internal)");
     if ((size_t)a.L.words * sizeof(float) > 65536) return fail(SAGMS_EUNSUPPORTED, "graph too large for one wave's LDS");
-    const int wpb = waves_per_block(a.L);
+    const int wpb = waves_per_block(a.L, CPL);
     const size_t lds = (size_t)wpb * a.L.words * sizeof(float);
     int rc;
     if (bp)
